@@ -1,0 +1,25 @@
+"""CPU oracle for the PDHG SDP method -- TEST INFRASTRUCTURE ONLY.
+
+Plain float64 NumPy with a full eigendecomposition every iteration.  Only
+the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package; the GPU library never does, and the
+two share no code (only the seeded input generators in ``instances``).
+
+Parity status per function (pins live in tests/test_oracle_*.py):
+  svec/smat, Operators.apply/adjoint   pinned (adjointness, dense brute force)
+  Operators.norm                       pinned (closed forms, dense SVD)
+  proj_psd, aproj_psd                  pinned (cone invariants, Eckart-Young,
+                                       2x2 and diagonal closed forms)
+  proj_box, dual_resolvent             pinned (scalar prox by direct minimisation)
+  pdhg_step, solve                     pinned (closed-form optima of K_n, C_n,
+                                       bipartite graphs; brute-force max-cut and
+                                       bisection brackets; KKT at convergence)
+  certificate                          pinned (vanishes at closed-form optima,
+                                       positive at perturbed points)
+  maxcut_bracket                       pinned (brackets closed-form values)
+"""
+from .sdp import *  # noqa: F401,F403
+from .sdp import (CONVERGED, MAX_ITERS, NUMERICAL, TIME_LIMIT, Certificate, Operators,  # noqa
+                  SolveResult, aproj_psd, brute_force_maxcut, brute_force_min_bisection,
+                  certificate, dense_sym_from_coo, dual_resolvent, eig_desc, maxcut_bracket,
+                  pdhg_step, proj_box, proj_psd, smat, solve, svec, svec_index)
