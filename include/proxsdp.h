@@ -1,0 +1,233 @@
+/*
+ * proxsdp.h -- C interface of a GPU (MI355X, gfx950) implementation of the
+ * primal-dual hybrid gradient method for general semidefinite programs with
+ * approximate (truncated, adaptive-rank) projection onto the PSD cone.
+ *
+ * Method: Souto, Garcia, Veiga, "Exploiting Low-Rank Structure in
+ * Semidefinite Programming by Approximate Operator Splitting"
+ * (arXiv 1810.05231):
+ *   problem          Section 1.3, general SDP form:
+ *                      minimize tr(C X)  s.t.  A(X) = b, G(X) <= h, X PSD
+ *   dual             Section 1.3 (dual problem; inequality duals <= 0)
+ *   iteration        Section 2.2 fixed-point iteration, Algorithm 1 (PD-SDP)
+ *   residuals        Section 2.2 (primal, dual, combined residual)
+ *   aproj            Section 3.1, truncated eigen-projection (eq_trunc_eig)
+ *   rank control     Section 3.2, Algorithm 2 (LR-PD-SDP)
+ *
+ * Conventions shared by every call:
+ *  - All functions return an int: PROXSDP_OK (0) or a negative error code.
+ *    proxsdp_last_error() returns a thread-local message for the last error.
+ *  - Symmetric matrices are passed by their upper triangle (i <= j) as
+ *    0-based COO triplets.  An off-diagonal triplet v at (i, j) stands for v
+ *    at (i, j) and at (j, i), so it contributes 2 v X_ij to tr(A X).
+ *    Duplicated triplets are summed.  A triplet with i > j, an index out of
+ *    range or a non-finite value is rejected with PROXSDP_ERR_INVALID.
+ *  - Constraint rows 0..m-1 are equalities A(X) = b, rows m..m+p-1 are
+ *    inequalities G(X) <= h.  A row is the sum of its triplets and of its
+ *    rank-one terms sigma * u u^T.
+ *  - The dual vector y has the sign of the Section 1.3 dual problem:
+ *    inequality duals are <= 0 and the dual constraint reads
+ *    C - sum_i y_i M_i PSD.  (Algorithm 1's y is the negative of this y.)
+ *  - Host arrays passed to a call are read during the call and copied; the
+ *    caller may free them on return.
+ *  - Device memory is the caller's: every call that needs device memory
+ *    takes a workspace pointer and size.  The library never allocates or
+ *    frees device memory and never frees the caller's memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Work
+ *    is enqueued on it; calls that return host results synchronise it.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef PROXSDP_H
+#define PROXSDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ codes */
+#define PROXSDP_OK 0
+#define PROXSDP_ERR_INVALID (-1)       /* bad argument or problem data        */
+#define PROXSDP_ERR_WORKSPACE (-2)     /* workspace NULL, misaligned or small */
+#define PROXSDP_ERR_HIP (-3)           /* a HIP runtime call failed           */
+#define PROXSDP_ERR_UNSUPPORTED (-4)   /* valid input outside supported sizes */
+
+/* solver status (proxsdp_info.status) */
+#define PROXSDP_STATUS_RUNNING 0       /* step() returned before a stop      */
+#define PROXSDP_STATUS_CONVERGED 1     /* residual and rank tests passed     */
+#define PROXSDP_STATUS_MAX_ITERS 2
+#define PROXSDP_STATUS_TIME_LIMIT 3
+#define PROXSDP_STATUS_NUMERICAL 4     /* NaN/Inf in the iterate             */
+
+/* storage / arithmetic of the dense n x n iterate and its block products */
+#define PROXSDP_FP64 0
+#define PROXSDP_FP32 1
+#define PROXSDP_BF16 2
+
+/* --------------------------------------------------------- problem */
+/* General SDP form, Section 1.3.  All pointers are host pointers. */
+typedef struct {
+  int32_t n;            /* X is n x n symmetric, n >= 1                       */
+  int32_t m;            /* number of equality rows (A(X) = b)                 */
+  int32_t p;            /* number of inequality rows (G(X) <= h)              */
+  int64_t nnz_c;        /* C as upper-triangle triplets                        */
+  const int32_t *c_i, *c_j;
+  const double *c_v;
+  int64_t nnz_a;        /* constraint triplets; a_row in [0, m + p)           */
+  const int32_t *a_row, *a_i, *a_j;
+  const double *a_v;
+  int32_t n_r1;         /* rank-one terms sigma_t u_t u_t^T added to row r1_row[t] */
+  const int32_t *r1_row;
+  const double *r1_sigma;
+  const double *r1_u;   /* n_r1 x n, row-major                                 */
+  const double *b;      /* m values                                            */
+  const double *h;      /* p values                                            */
+} proxsdp_problem;
+
+/* ----------------------------------------------------------- options */
+typedef struct {
+  double tol;           /* stop when max(rho_p, rho_d) <= tol (default 1e-4); rho as
+                           in proxsdp_info                                      */
+  double eps_lambda;    /* rank test (n - r) max(lambda_r, 0) <= eps_lambda of
+                           Algorithm 2; < 0 means eps_lambda = tol (default -1) */
+  double alpha;         /* step size; 0 = 0.95 / ||M||_2 of the row-scaled operator
+                           (Section 2.2 requires 0 < alpha < 1/||M||_2)         */
+  int32_t window;       /* l of Algorithm 2's windowed residual test (default 50);
+                           must be a multiple of check_every                     */
+  int32_t check_every;  /* iterations between host-side control checks (10)     */
+  int32_t r0;           /* initial target rank (default 1, Algorithm 2)          */
+  int32_t r_max;        /* largest target rank (0 = automatic)                   */
+  int32_t full_eig;     /* 1 = PD-SDP (Algorithm 1, exact projection; n <= 64)   */
+  int32_t precision;    /* PROXSDP_FP64 (default), PROXSDP_FP32, PROXSDP_BF16    */
+  int32_t max_iters;    /* default 200000                                        */
+  double time_limit_s;  /* default 1200 (the paper's cap); <= 0 = none           */
+  int32_t row_scaling;  /* 1 (default): rows scaled to unit Frobenius norm        */
+  int32_t block;        /* subspace width k (0 = automatic, multiple of 16)       */
+  double eig_tol;       /* relative Ritz residual target of the partial
+                           eigensolve, floor of the adaptive schedule (1e-10)    */
+  int32_t max_passes;   /* max dense passes per iteration (default 8)             */
+  int32_t seed;         /* seed of the initial random subspace (default 1)        */
+  int32_t eig_strict;   /* 1: every iteration repeats eigensolver rounds until the
+                           kept Ritz pairs meet eig_tol (synchronises per round;
+                           for verification), 0 (default): adaptive schedule    */
+} proxsdp_options;
+
+/* ------------------------------------------------------------- info */
+typedef struct {
+  int32_t status;       /* PROXSDP_STATUS_*                                       */
+  int32_t iters;        /* PDHG iterations done since create                      */
+  int32_t r;            /* current target rank                                    */
+  int32_t k;            /* current subspace width                                  */
+  int32_t rank_updates; /* number of r <- 2r updates so far                       */
+  int32_t passes;       /* total dense passes over the n x n iterate               */
+  double lambda_r;      /* r-th largest eigenvalue of the last projected matrix   */
+  double lambda_r1;     /* (r+1)-th (first excluded) Ritz value, or NaN            */
+  double eps_p, eps_d;  /* Section 2.2 residuals of the last iteration (scaled rows) */
+  double rho_p, rho_d;  /* eps_p / (1 + ||C||_F), eps_d / (1 + ||[b; h]||_2)       */
+  double obj;           /* tr(C X) at the last check                               */
+  double dual_obj;      /* b^T y_eq + h^T y_ineq at the last check                 */
+  double alpha;         /* step size in use                                        */
+  double norm_M;        /* ||M||_2 of the (scaled) operator                        */
+  double ritz_res;      /* largest relative Ritz residual of the kept pairs        */
+  double time_s;        /* wall time inside step/solve since create                */
+} proxsdp_info;
+
+typedef struct proxsdp_handle proxsdp_handle;
+
+/* Fills *opt with the defaults listed above. */
+int proxsdp_default_options(proxsdp_options *opt);
+
+/* Device workspace (bytes) that proxsdp_create needs for this problem and these
+ * options.  Validates the problem (same checks as create); host-only, makes
+ * no HIP call. */
+int proxsdp_workspace_size(const proxsdp_problem *prob, const proxsdp_options *opt,
+                           size_t *bytes);
+
+/* Builds a solver: validates and preprocesses the data (duplicate summing,
+ * row scaling, sparsity pattern, ||M||_2 and alpha), uploads it into
+ * d_workspace (device memory of at least proxsdp_workspace_size bytes,
+ * 256-byte aligned) and sets X0 = 0, y0 = 0.  The workspace must stay valid
+ * and untouched until proxsdp_destroy.  Enqueues on `stream` and
+ * synchronises it before returning. */
+int proxsdp_create(const proxsdp_problem *prob, const proxsdp_options *opt, void *d_workspace,
+                   size_t ws_bytes, void *stream, proxsdp_handle **out);
+
+/* Runs up to n_iters PDHG iterations (Algorithm 2's inner loop, with its rank
+ * control every check_every iterations) and stops early on a terminal
+ * status.  If info != NULL the stream is synchronised and *info filled. */
+int proxsdp_step(proxsdp_handle *h, int32_t n_iters, proxsdp_info *info);
+
+/* Iterates until a terminal status (converged, iteration or time limit,
+ * numerical failure); fills *info (may be NULL).  Synchronises. */
+int proxsdp_solve(proxsdp_handle *h, proxsdp_info *info);
+
+/* Current iterate: X (n x n, row-major, formed from the rank-r factors) and
+ * the dual y (m + p values, unscaled, Section 1.3 sign).  Either pointer may
+ * be NULL.  on_device = 0: host pointers; 1: device pointers.  Synchronises. */
+int proxsdp_get_solution(proxsdp_handle *h, double *X, double *y, int32_t on_device);
+
+/* Current factors X = V diag(lambda) V^T: V is n x r row-major (lds = r),
+ * lambda has r values (>= 0).  Host pointers; either may be NULL.  *r_out gets r. */
+int proxsdp_get_factors(proxsdp_handle *h, double *V, double *lambda, int32_t *r_out);
+
+/* Restarts the iteration from X0 = 0, y0 = 0 (Algorithm 2 with r = r0) on the
+ * problem data already on the device; no host transfer of problem data.
+ * Synchronises the stream. */
+int proxsdp_reset(proxsdp_handle *h);
+
+/* Kernel timing for benchmarks: enable = 1 records HIP events on the handle's
+ * stream around every dense pass W B and every dense write of W (up to 8192
+ * launches each); proxsdp_profile_read synchronises, returns the summed
+ * milliseconds and launch counts since enabling, and stops recording.
+ * Any pointer may be NULL. */
+int proxsdp_profile_enable(proxsdp_handle *h, int32_t enable);
+int proxsdp_profile_read(proxsdp_handle *h, double *pass_ms, int32_t *pass_count,
+                         double *write_ms, int32_t *write_count);
+
+/* Diagnostics: copies min(count, 64) internal device scalars to host `out`
+ * (0 step size, 1 lower spectral bound used by the filter, 2 largest relative
+ * Ritz residual of the kept pairs, 3 lambda_r, 4 lambda_{r+1}, 5 max |theta|,
+ * 6 eps_p, 7 eps_d, 8 objective, 9 dual objective, 10 ||X+ - X||_F^2,
+ * 13 non-finite code (0 none, 1 Rayleigh-Ritz, 2 full eigensolve, 3 dual
+ * step, 4 residuals), 14 dropped basis columns, 15 filter centre, 16 filter
+ * half-width, 17 Jacobi sweeps) followed by the Ritz values of the last
+ * Rayleigh-Ritz step in out[64 ..] if count > 64.  Synchronises. */
+int proxsdp_debug_scalars(proxsdp_handle *h, double *out, int32_t count);
+
+/* Releases host-side state.  Does not touch the caller's workspace. */
+void proxsdp_destroy(proxsdp_handle *h);
+
+/* --------------------------------------------------- projection only */
+/* Device workspace (bytes) for proxsdp_project_psd with these sizes. */
+int proxsdp_project_workspace_size(int32_t n, int32_t r, int32_t precision, size_t *bytes);
+
+/* aproj(S, r) of Section 3.1 (eq_trunc_eig): sum over the r algebraically
+ * largest eigenvalues lambda_i of the symmetric S of max(0, lambda_i) u_i u_i^T;
+ * r = 0 or r >= n gives the exact projection of Section 2.3.2 (n <= 64);
+ * for n > 64 the target rank must be <= 48.
+ *   S       device, n x n row-major with leading dimension lds >= n, FP64
+ *           (precision = PROXSDP_FP64); only read.  Must be symmetric.
+ *   P       device, n x n output with leading dimension ldp, or NULL.
+ *   evals   host, r values: the r largest eigenvalues, decreasing (or NULL).
+ *   evecs   host, n x r row-major eigenvectors (or NULL).
+ *   rank_out host: number of positive eigenvalues kept (or NULL).
+ *   tol     relative residual target ||S v - lambda v|| <= tol ||S||_2 of the kept
+ *           pairs (<= 0: 1e-12).
+ * Synchronises `stream`.  Returns PROXSDP_ERR_UNSUPPORTED if the iteration does
+ * not reach tol within its pass budget. */
+int proxsdp_project_psd(const void *S, int32_t n, int64_t lds, int32_t r, int32_t precision,
+                        double tol, void *P, int64_t ldp, double *evals, double *evecs,
+                        int32_t *rank_out, void *d_workspace, size_t ws_bytes, void *stream);
+
+/* Thread-local description of the last error (empty string if none). */
+const char *proxsdp_last_error(void);
+
+/* Library version string. */
+const char *proxsdp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PROXSDP_H */

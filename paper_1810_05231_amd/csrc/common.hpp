@@ -1,0 +1,109 @@
+// Shared constants and device-side layouts of libproxsdp.
+//
+// Memory layout (device, carved from the caller's workspace):
+//  * W, the matrix the primal step projects (Algorithm 1: X - alpha (C - M*(y))
+//    in the dual sign of Section 1.3), is npad x npad row-major, npad = n
+//    rounded up to TILE.  Rows/columns >= n are zero.
+//  * Subspace blocks (basis B, product Z = W B, Chebyshev iterates) are
+//    npad x k row-major with row stride k; rows >= n are zero.
+//  * Factors V of X = V diag(lambda) V^T are npad x KMAX (row stride KMAX).
+//  * Small matrices (k x k) are row-major with row stride KMAX.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace proxsdp {
+
+constexpr int TILE = 64;      // dense write tile and padding unit
+constexpr int KMAX = 64;      // largest subspace width / largest n of the full-eig path
+constexpr int SLICE = 64;     // rows per workgroup in the row-wise kernels
+constexpr int MAX_R1 = 4;     // largest number of rank-one constraint terms
+constexpr int RING = 1024;    // per-iteration record ring
+
+// Offsets (in doubles) inside the `small` device block.
+struct SL {
+  static constexpr int kk = KMAX * KMAX;
+  static constexpr int S = 0;                  // Ritz coefficients, V = B S
+  static constexpr int MZ = S + kk;            // next basis Bn = Z MZ + B MB
+  static constexpr int MB = MZ + kk;
+  static constexpr int THETA = MB + kk;        // Ritz values, decreasing
+  static constexpr int RES = THETA + KMAX;     // relative Ritz residuals
+  static constexpr int LAM = RES + KMAX;       // 2 x KMAX: lambda_+ by iteration parity
+  static constexpr int GG = LAM + 2 * KMAX;    // reduced Grams B^T B, B^T Z, Z^T Z
+  static constexpr int TG = GG + kk;
+  static constexpr int PG = TG + kk;
+  static constexpr int SC = PG + kk;           // named scalars
+  static constexpr int TOTAL = SC + 64;
+};
+
+enum Scalar {
+  S_ALPHA = 0,    // step size
+  S_GERSH,        // lower bound of lambda_min(W) from the sparse + rank-one part
+  S_MAXRES,       // largest relative Ritz residual of the kept pairs (last RR)
+  S_LAMR,         // r-th Ritz value
+  S_LAMR1,        // (r+1)-th Ritz value (NaN if none)
+  S_NORMW,        // max |theta|
+  S_EPSP,         // residuals of the last finalised iteration
+  S_EPSD,
+  S_OBJ,
+  S_DOBJ,
+  S_DX2,
+  S_X2,           // 2 slots by parity: ||X||_F^2
+  S_X2B,
+  S_NONFINITE,    // 0 ok; 1 Rayleigh-Ritz, 2 full eig, 3 dual step, 4 residuals
+  S_CHOLFIX,      // number of regularised Cholesky pivots in the last RR
+  S_FILTC,
+  S_FILTE,
+  S_SWEEPS,       // Jacobi sweeps of the last small eigensolve
+  S_COUNT
+};
+
+// One record per iteration (written by the finalising workgroup).
+struct IterRecord {
+  double eps_p, eps_d, obj, dual_obj;
+  double lambda_r, lambda_r1, maxres, gersh;
+};
+
+// Device views of the preprocessed problem.
+struct DevProblem {
+  int n, npad, rows, m, p;
+  int n_pat;
+  const int* pat_a;       // entry (a, b), a <= b
+  const int* pat_b;
+  const double* pat_c;    // C on the entry
+  const int* pat_rptr;    // entry -> rows CSR
+  const int* pat_row;
+  const double* pat_val;  // scaled coefficient (matrix value, not doubled)
+  const int* row_ptr;     // row -> entries CSR
+  const int* row_a;
+  const int* row_b;
+  const double* row_w;    // scaled coefficient, x2 off the diagonal
+  const int* sym_ptr;     // symmetric rows of the pattern (n + 1)
+  const int* sym_e;
+  int tiles_side;         // npad / TILE
+  const int* tile_ptr;    // full (mirrored) pattern bucketed by tile
+  const int* tile_item;   // (local row << 8) | local col
+  const int* tile_e;
+  int n_r1;
+  int r1_row[MAX_R1];
+  double r1_sigma[MAX_R1];  // scaled sigma
+  double r1_norm2[MAX_R1];  // ||u||^2
+  double r1_gram[MAX_R1 * MAX_R1];  // (u_s^T u_t)^2
+  const double* r1_u;     // n_r1 x npad
+  const int* row_r1;      // rows: rank-one term index or -1
+  const double* rhs;      // [b; h] scaled
+};
+
+// Partial-buffer strides (doubles per slice / per block).
+constexpr int FAC_RES = 2 * KMAX * KMAX + MAX_R1 * KMAX;   // Ritz residual norms^2 (k values)
+constexpr int FAC_STRIDE = FAC_RES + KMAX;
+constexpr int ROW_PART = 4;                 // eps_d^2, <dMX, dy>, dual obj, nonfinite
+constexpr int PAT_PART = 4 + MAX_R1;        // min gersh, ||M*dy||^2 (sparse), obj, unused, cross_q
+
+// Number of SLICE-row workgroups covering npad rows.
+inline int n_slices(int npad) { return (npad + SLICE - 1) / SLICE; }
+
+}  // namespace proxsdp

@@ -1,0 +1,1323 @@
+// libproxsdp: host side of the C interface declared in include/proxsdp.h.
+//
+// One process drives one GPU.  The host validates and preprocesses the
+// problem once (create), then enqueues the per-iteration kernel schedule on
+// the caller's stream and only synchronises at control checks (every
+// `check_every` iterations), where it applies the rank control of
+// Algorithm 2 (Section 3.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/proxsdp.h"
+#include "common.hpp"
+#include "dense.hpp"
+#include "small.hpp"
+#include "sparse.hpp"
+
+using namespace proxsdp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_OK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(PROXSDP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline int roundup(int x, int m) { return (x + m - 1) / m * m; }
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// --------------------------------------------------------------- preprocessing
+struct Host {
+  int n = 0, npad = 0, m = 0, p = 0, rows = 0;
+  std::vector<int> pat_a, pat_b;
+  std::vector<double> pat_c;
+  std::vector<int> pat_rptr, pat_row;
+  std::vector<double> pat_val;
+  std::vector<int> row_ptr, row_a, row_b;
+  std::vector<double> row_w;
+  std::vector<int> sym_ptr, sym_e;
+  std::vector<int> tile_ptr, tile_item, tile_e;
+  int n_r1 = 0;
+  std::vector<int> r1_row;
+  std::vector<double> r1_sigma, r1_u, r1_norm2, r1_gram;
+  std::vector<int> row_r1;
+  std::vector<double> rhs, scale;
+  double norm_c = 0, norm_rhs = 0, norm_m = 0;
+};
+
+bool finite_all(const double* v, int64_t cnt) {
+  for (int64_t i = 0; i < cnt; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+int validate(const proxsdp_problem* pb, const proxsdp_options* o) {
+  if (!pb) return fail(PROXSDP_ERR_INVALID, "problem is NULL");
+  if (pb->n < 1) return fail(PROXSDP_ERR_INVALID, "n must be >= 1");
+  if (pb->m < 0 || pb->p < 0) return fail(PROXSDP_ERR_INVALID, "m and p must be >= 0");
+  if (pb->m + pb->p < 1) return fail(PROXSDP_ERR_INVALID, "at least one constraint row required");
+  if (pb->nnz_c < 0 || pb->nnz_a < 0 || pb->n_r1 < 0)
+    return fail(PROXSDP_ERR_INVALID, "negative count");
+  if (pb->nnz_c > 0 && (!pb->c_i || !pb->c_j || !pb->c_v))
+    return fail(PROXSDP_ERR_INVALID, "C arrays are NULL");
+  if (pb->nnz_a > 0 && (!pb->a_row || !pb->a_i || !pb->a_j || !pb->a_v))
+    return fail(PROXSDP_ERR_INVALID, "constraint arrays are NULL");
+  if (pb->m > 0 && !pb->b) return fail(PROXSDP_ERR_INVALID, "b is NULL");
+  if (pb->p > 0 && !pb->h) return fail(PROXSDP_ERR_INVALID, "h is NULL");
+  if (pb->n_r1 > MAX_R1)
+    return fail(PROXSDP_ERR_UNSUPPORTED, "at most " + std::to_string(MAX_R1) + " rank-one terms");
+  if (pb->n_r1 > 0 && (!pb->r1_row || !pb->r1_sigma || !pb->r1_u))
+    return fail(PROXSDP_ERR_INVALID, "rank-one arrays are NULL");
+  const int n = pb->n, rows = pb->m + pb->p;
+  for (int64_t t = 0; t < pb->nnz_c; ++t) {
+    const int i = pb->c_i[t], j = pb->c_j[t];
+    if (i < 0 || j < 0 || i >= n || j >= n) return fail(PROXSDP_ERR_INVALID, "C index out of range");
+    if (i > j) return fail(PROXSDP_ERR_INVALID, "C entry below the diagonal (need i <= j)");
+  }
+  for (int64_t t = 0; t < pb->nnz_a; ++t) {
+    const int r = pb->a_row[t], i = pb->a_i[t], j = pb->a_j[t];
+    if (r < 0 || r >= rows) return fail(PROXSDP_ERR_INVALID, "constraint row out of range");
+    if (i < 0 || j < 0 || i >= n || j >= n)
+      return fail(PROXSDP_ERR_INVALID, "constraint index out of range");
+    if (i > j) return fail(PROXSDP_ERR_INVALID, "constraint entry below the diagonal (need i <= j)");
+  }
+  if (!finite_all(pb->c_v, pb->nnz_c) || !finite_all(pb->a_v, pb->nnz_a) ||
+      !finite_all(pb->b, pb->m) || !finite_all(pb->h, pb->p))
+    return fail(PROXSDP_ERR_INVALID, "non-finite problem data");
+  std::vector<int> seen(rows, 0);
+  for (int q = 0; q < pb->n_r1; ++q) {
+    const int r = pb->r1_row[q];
+    if (r < 0 || r >= rows) return fail(PROXSDP_ERR_INVALID, "rank-one row out of range");
+    if (seen[r]++) return fail(PROXSDP_ERR_UNSUPPORTED, "at most one rank-one term per row");
+    if (!std::isfinite(pb->r1_sigma[q]) || !finite_all(pb->r1_u + (int64_t)q * n, n))
+      return fail(PROXSDP_ERR_INVALID, "non-finite rank-one data");
+  }
+  if (o) {
+    if (!(o->tol > 0)) return fail(PROXSDP_ERR_INVALID, "tol must be > 0");
+    if (o->check_every < 1 || o->window < o->check_every || o->window % o->check_every)
+      return fail(PROXSDP_ERR_INVALID, "window must be a positive multiple of check_every");
+    if (o->precision != PROXSDP_FP64)
+      return fail(PROXSDP_ERR_UNSUPPORTED, "only PROXSDP_FP64 storage is built in this library");
+    if (o->alpha < 0) return fail(PROXSDP_ERR_INVALID, "alpha must be >= 0");
+    if (o->full_eig && pb->n > KMAX)
+      return fail(PROXSDP_ERR_UNSUPPORTED, "full_eig needs n <= " + std::to_string(KMAX));
+    if (o->block && (o->block % 16 || o->block > KMAX))
+      return fail(PROXSDP_ERR_INVALID, "block must be a multiple of 16 and <= 64");
+  }
+  return PROXSDP_OK;
+}
+
+// K y for the Gram operator K = M M* of the (scaled) rows, on the host.
+struct GramOp {
+  const Host& h;
+  explicit GramOp(const Host& hh) : h(hh) {}
+  void apply(const std::vector<double>& y, std::vector<double>& out) const {
+    const int npat = (int)h.pat_a.size();
+    std::vector<double> s(npat, 0.0);
+    for (int e = 0; e < npat; ++e) {
+      double acc = 0.0;
+      for (int t = h.pat_rptr[e]; t < h.pat_rptr[e + 1]; ++t) acc += y[h.pat_row[t]] * h.pat_val[t];
+      s[e] = acc;
+    }
+    std::vector<double> cq(h.n_r1);
+    for (int q = 0; q < h.n_r1; ++q) cq[q] = h.r1_sigma[q] * y[h.r1_row[q]];
+    const int np = h.npad;
+    out.assign(h.rows, 0.0);
+    // Sparse-sparse part through entry ids: iterate entries once.
+    for (int e = 0; e < npat; ++e) {
+      const double w = (h.pat_a[e] == h.pat_b[e]) ? 1.0 : 2.0;
+      double rank1 = 0.0;
+      for (int q = 0; q < h.n_r1; ++q)
+        rank1 += cq[q] * h.r1_u[(size_t)q * np + h.pat_a[e]] * h.r1_u[(size_t)q * np + h.pat_b[e]];
+      for (int t = h.pat_rptr[e]; t < h.pat_rptr[e + 1]; ++t)
+        out[h.pat_row[t]] += w * h.pat_val[t] * (s[e] + rank1);
+    }
+    for (int q = 0; q < h.n_r1; ++q) {
+      double acc = 0.0;
+      for (int e = 0; e < npat; ++e) {
+        const double w = (h.pat_a[e] == h.pat_b[e]) ? 1.0 : 2.0;
+        acc += w * s[e] * h.r1_u[(size_t)q * np + h.pat_a[e]] * h.r1_u[(size_t)q * np + h.pat_b[e]];
+      }
+      for (int q2 = 0; q2 < h.n_r1; ++q2) acc += cq[q2] * h.r1_gram[q * MAX_R1 + q2];
+      out[h.r1_row[q]] += h.r1_sigma[q] * acc;
+    }
+  }
+};
+
+// Largest eigenvalue of a symmetric tridiagonal matrix by bisection (Sturm count).
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int k = (int)a.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_greater = [&](double x) {
+    int c = 0;
+    double d = 1.0;
+    for (int i = 0; i < k; ++i) {
+      const double bb = (i > 0) ? b[i - 1] * b[i - 1] : 0.0;
+      d = (a[i] - x) - ((i > 0) ? bb / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d > 0) ++c;
+    }
+    return c;  // number of eigenvalues > x
+  };
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_greater(mid) > 0) lo = mid; else hi = mid;
+    if (hi - lo <= 1e-15 * std::max(1.0, std::fabs(hi))) break;
+  }
+  return hi;
+}
+
+// ||M||_2 = sqrt(lambda_max(K)) by Lanczos on K (no reorthogonalisation: the
+// extreme Ritz value is unaffected by the loss of orthogonality).
+double op_norm(const Host& h) {
+  GramOp K(h);
+  const int rows = h.rows;
+  std::vector<double> v(rows), w, vprev(rows, 0.0);
+  for (int i = 0; i < rows; ++i) v[i] = 1.0 + 0.5 * std::sin(1.0 + 0.37 * i);
+  double nv = 0;
+  for (double x : v) nv += x * x;
+  nv = std::sqrt(nv);
+  for (double& x : v) x /= nv;
+  std::vector<double> al, be;
+  double beta = 0.0, last = 0.0;
+  const int steps = std::min(rows, 120);
+  for (int it = 0; it < steps; ++it) {
+    K.apply(v, w);
+    double a = 0;
+    for (int i = 0; i < rows; ++i) a += w[i] * v[i];
+    for (int i = 0; i < rows; ++i) w[i] -= a * v[i] + beta * vprev[i];
+    double b = 0;
+    for (double x : w) b += x * x;
+    b = std::sqrt(b);
+    al.push_back(a);
+    const double est = tridiag_max_eig(al, be);
+    if (it > 5 && std::fabs(est - last) <= 1e-14 * std::fabs(est)) { last = est; break; }
+    last = est;
+    if (b <= 1e-14 * std::fabs(est)) break;
+    be.push_back(b);
+    vprev = v;
+    for (int i = 0; i < rows; ++i) v[i] = w[i] / b;
+    beta = b;
+  }
+  return std::sqrt(std::max(last, 0.0));
+}
+
+int preprocess(const proxsdp_problem* pb, int row_scaling, Host& h) {
+  const int n = pb->n;
+  h.n = n;
+  h.npad = roundup(n, TILE);
+  h.m = pb->m;
+  h.p = pb->p;
+  h.rows = pb->m + pb->p;
+  // pattern keys
+  struct Trip { int64_t key; int row; double v; };
+  std::vector<Trip> ct(pb->nnz_c), at(pb->nnz_a);
+  for (int64_t t = 0; t < pb->nnz_c; ++t)
+    ct[t] = {(int64_t)pb->c_i[t] * n + pb->c_j[t], -1, pb->c_v[t]};
+  for (int64_t t = 0; t < pb->nnz_a; ++t)
+    at[t] = {(int64_t)pb->a_i[t] * n + pb->a_j[t], pb->a_row[t], pb->a_v[t]};
+  std::vector<int64_t> keys;
+  keys.reserve(ct.size() + at.size());
+  for (auto& t : ct) keys.push_back(t.key);
+  for (auto& t : at) keys.push_back(t.key);
+  std::sort(keys.begin(), keys.end());
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  const int npat = (int)keys.size();
+  auto eid = [&](int64_t key) {
+    return (int)(std::lower_bound(keys.begin(), keys.end(), key) - keys.begin());
+  };
+  h.pat_a.resize(npat);
+  h.pat_b.resize(npat);
+  h.pat_c.assign(npat, 0.0);
+  for (int e = 0; e < npat; ++e) {
+    h.pat_a[e] = (int)(keys[e] / n);
+    h.pat_b[e] = (int)(keys[e] % n);
+  }
+  for (auto& t : ct) h.pat_c[eid(t.key)] += t.v;
+  // (row, entry, v) merged
+  struct RE { int row, e; double v; };
+  std::vector<RE> re(at.size());
+  for (size_t t = 0; t < at.size(); ++t) re[t] = {at[t].row, eid(at[t].key), at[t].v};
+  std::sort(re.begin(), re.end(), [](const RE& x, const RE& y) {
+    return x.row != y.row ? x.row < y.row : x.e < y.e;
+  });
+  std::vector<RE> mr;
+  for (auto& x : re) {
+    if (!mr.empty() && mr.back().row == x.row && mr.back().e == x.e) mr.back().v += x.v;
+    else mr.push_back(x);
+  }
+  // rank-one terms
+  h.n_r1 = pb->n_r1;
+  h.r1_row.assign(pb->r1_row, pb->r1_row + h.n_r1);
+  h.r1_sigma.assign(pb->r1_sigma, pb->r1_sigma + h.n_r1);
+  h.r1_u.assign((size_t)std::max(h.n_r1, 1) * h.npad, 0.0);
+  for (int q = 0; q < h.n_r1; ++q)
+    for (int i = 0; i < n; ++i) h.r1_u[(size_t)q * h.npad + i] = pb->r1_u[(size_t)q * n + i];
+  h.row_r1.assign(h.rows, -1);
+  for (int q = 0; q < h.n_r1; ++q) h.row_r1[h.r1_row[q]] = q;
+  // row norms ||M_i||_F
+  h.scale.assign(h.rows, 0.0);
+  std::vector<double> nrm2(h.rows, 0.0);
+  for (auto& x : mr) {
+    const double w = (h.pat_a[x.e] == h.pat_b[x.e]) ? 1.0 : 2.0;
+    nrm2[x.row] += w * x.v * x.v;
+  }
+  h.r1_norm2.assign(MAX_R1, 0.0);
+  for (int q = 0; q < h.n_r1; ++q) {
+    double s = 0;
+    for (int i = 0; i < n; ++i) s += h.r1_u[(size_t)q * h.npad + i] * h.r1_u[(size_t)q * h.npad + i];
+    h.r1_norm2[q] = s;
+    const int row = h.r1_row[q];
+    const double sg = h.r1_sigma[q];
+    double crossv = 0.0;
+    for (auto& x : mr) {
+      if (x.row != row) continue;
+      const double w = (h.pat_a[x.e] == h.pat_b[x.e]) ? 1.0 : 2.0;
+      crossv += w * x.v * h.r1_u[(size_t)q * h.npad + h.pat_a[x.e]] *
+                h.r1_u[(size_t)q * h.npad + h.pat_b[x.e]];
+    }
+    nrm2[row] += 2.0 * sg * crossv + sg * sg * s * s;
+  }
+  for (int i = 0; i < h.rows; ++i) {
+    if (!(nrm2[i] > 0.0)) return fail(PROXSDP_ERR_INVALID, "constraint row " + std::to_string(i) + " is zero");
+    h.scale[i] = row_scaling ? std::sqrt(nrm2[i]) : 1.0;
+  }
+  for (auto& x : mr) x.v /= h.scale[x.row];
+  for (int q = 0; q < h.n_r1; ++q) h.r1_sigma[q] /= h.scale[h.r1_row[q]];
+  h.r1_gram.assign(MAX_R1 * MAX_R1, 0.0);
+  for (int q = 0; q < h.n_r1; ++q)
+    for (int q2 = 0; q2 < h.n_r1; ++q2) {
+      double s = 0;
+      for (int i = 0; i < n; ++i) s += h.r1_u[(size_t)q * h.npad + i] * h.r1_u[(size_t)q2 * h.npad + i];
+      h.r1_gram[q * MAX_R1 + q2] = s * s;
+    }
+  h.rhs.resize(h.rows);
+  for (int i = 0; i < h.m; ++i) h.rhs[i] = pb->b[i] / h.scale[i];
+  for (int i = 0; i < h.p; ++i) h.rhs[h.m + i] = pb->h[i] / h.scale[h.m + i];
+  // row -> entries
+  h.row_ptr.assign(h.rows + 1, 0);
+  for (auto& x : mr) h.row_ptr[x.row + 1]++;
+  for (int i = 0; i < h.rows; ++i) h.row_ptr[i + 1] += h.row_ptr[i];
+  h.row_a.resize(mr.size());
+  h.row_b.resize(mr.size());
+  h.row_w.resize(mr.size());
+  for (size_t t = 0; t < mr.size(); ++t) {
+    const int e = mr[t].e;
+    h.row_a[t] = h.pat_a[e];
+    h.row_b[t] = h.pat_b[e];
+    h.row_w[t] = mr[t].v * ((h.pat_a[e] == h.pat_b[e]) ? 1.0 : 2.0);
+  }
+  // entry -> rows
+  h.pat_rptr.assign(npat + 1, 0);
+  for (auto& x : mr) h.pat_rptr[x.e + 1]++;
+  for (int e = 0; e < npat; ++e) h.pat_rptr[e + 1] += h.pat_rptr[e];
+  h.pat_row.resize(mr.size());
+  h.pat_val.resize(mr.size());
+  {
+    std::vector<int> fill(h.pat_rptr.begin(), h.pat_rptr.end() - 1);
+    for (auto& x : mr) {
+      const int pos = fill[x.e]++;
+      h.pat_row[pos] = x.row;
+      h.pat_val[pos] = x.v;
+    }
+  }
+  // symmetric rows of the pattern
+  h.sym_ptr.assign(n + 1, 0);
+  for (int e = 0; e < npat; ++e) {
+    h.sym_ptr[h.pat_a[e] + 1]++;
+    if (h.pat_a[e] != h.pat_b[e]) h.sym_ptr[h.pat_b[e] + 1]++;
+  }
+  for (int i = 0; i < n; ++i) h.sym_ptr[i + 1] += h.sym_ptr[i];
+  h.sym_e.resize(h.sym_ptr[n]);
+  {
+    std::vector<int> fill(h.sym_ptr.begin(), h.sym_ptr.end() - 1);
+    for (int e = 0; e < npat; ++e) {
+      h.sym_e[fill[h.pat_a[e]]++] = e;
+      if (h.pat_a[e] != h.pat_b[e]) h.sym_e[fill[h.pat_b[e]]++] = e;
+    }
+  }
+  // tile lists of the mirrored pattern
+  const int ts = h.npad / TILE;
+  h.tile_ptr.assign((size_t)ts * ts + 1, 0);
+  auto tile_of = [&](int a, int b) { return (a / TILE) * ts + (b / TILE); };
+  for (int e = 0; e < npat; ++e) {
+    h.tile_ptr[tile_of(h.pat_a[e], h.pat_b[e]) + 1]++;
+    if (h.pat_a[e] != h.pat_b[e]) h.tile_ptr[tile_of(h.pat_b[e], h.pat_a[e]) + 1]++;
+  }
+  for (size_t t = 0; t + 1 < h.tile_ptr.size(); ++t) h.tile_ptr[t + 1] += h.tile_ptr[t];
+  h.tile_item.resize(h.tile_ptr.back());
+  h.tile_e.resize(h.tile_ptr.back());
+  {
+    std::vector<int> fill(h.tile_ptr.begin(), h.tile_ptr.end() - 1);
+    auto put = [&](int a, int b, int e) {
+      const int pos = fill[tile_of(a, b)]++;
+      h.tile_item[pos] = ((a % TILE) << 8) | (b % TILE);
+      h.tile_e[pos] = e;
+    };
+    for (int e = 0; e < npat; ++e) {
+      put(h.pat_a[e], h.pat_b[e], e);
+      if (h.pat_a[e] != h.pat_b[e]) put(h.pat_b[e], h.pat_a[e], e);
+    }
+  }
+  // norms
+  double nc = 0;
+  for (int e = 0; e < npat; ++e) {
+    const double w = (h.pat_a[e] == h.pat_b[e]) ? 1.0 : 2.0;
+    nc += w * h.pat_c[e] * h.pat_c[e];
+  }
+  h.norm_c = std::sqrt(nc);
+  double nr = 0;
+  for (double v : h.rhs) nr += v * v;
+  h.norm_rhs = std::sqrt(nr);
+  h.norm_m = op_norm(h);
+  if (!(h.norm_m > 0)) return fail(PROXSDP_ERR_INVALID, "constraint operator is zero");
+  return PROXSDP_OK;
+}
+
+// ------------------------------------------------------------- workspace
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align256(off + std::max<size_t>(count, 1) * sizeof(T));
+    return p;
+  }
+};
+
+int k_for_r(int r) {
+  int k = roundup(r + std::max(8, (r + 1) / 2), 16);
+  return std::min(k, KMAX);
+}
+
+struct Chunking {
+  int rows_per_chunk, nchunks;
+};
+
+Chunking chunking(int npad) {
+  const int cols = npad / 64;
+  const int target = std::max(1, (1024 + cols - 1) / cols);
+  int R = roundup((npad + target - 1) / target, 64);
+  R = std::max(R, 64);
+  return {R, (npad + R - 1) / R};
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+struct proxsdp_handle {
+  hipStream_t st = nullptr;
+  proxsdp_options opt{};
+  Host h;
+  DevProblem dp{};
+  int n = 0, npad = 0, rows = 0;
+  bool full = false;      // exact eigendecomposition path (n <= KMAX)
+  int k_cap = 16, r_cap = 1;
+  int k = 16, r = 1, r_old = 0;
+  Chunking ch{};
+  int nsl = 1, nrow_blocks = 1, npat_blocks = 1;
+  // device buffers
+  double* W = nullptr;
+  double* B[2] = {nullptr, nullptr};
+  int bcur = 0;
+  double* Z = nullptr;
+  double* part = nullptr;
+  double* gram_part = nullptr;
+  double* small = nullptr;
+  double* V[2] = {nullptr, nullptr};
+  double* fac_part = nullptr;
+  double *y = nullptr, *y_old = nullptr, *MX = nullptr, *MX_old = nullptr;
+  double *row_part = nullptr, *pat_part = nullptr, *dval = nullptr;
+  IterRecord* ring = nullptr;
+  // control
+  int iters = 0, passes = 0, rank_updates = 0;
+  int m_rounds = 2;
+  int status = PROXSDP_STATUS_RUNNING;
+  std::vector<double> hist;
+  double eps_lambda = 0;
+  double time_s = 0;
+  proxsdp_info last{};
+  size_t ws_need = 0;
+  // optional kernel timing (benchmarks)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pass, ev_write;   // start/stop pairs
+  int n_pass = 0, n_write = 0;
+  ~proxsdp_handle() {
+    for (auto e : ev_pass) (void)hipEventDestroy(e);
+    for (auto e : ev_write) (void)hipEventDestroy(e);
+  }
+};
+
+constexpr int PROF_MAX = 8192;
+
+static void prof_mark(proxsdp_handle* H, std::vector<hipEvent_t>& pool, int& cnt, bool start) {
+  if (!H->prof) return;
+  const int idx = 2 * cnt + (start ? 0 : 1);
+  if (cnt >= PROF_MAX || idx >= (int)pool.size()) return;
+  (void)hipEventRecord(pool[idx], H->st);
+  if (!start) ++cnt;
+}
+
+static size_t carve(proxsdp_handle* H, void* ws) {
+  const int npad = H->npad;
+  Carver c(ws);
+  const Host& h = H->h;
+  H->W = c.take<double>((size_t)npad * npad);
+  H->B[0] = c.take<double>((size_t)npad * H->k_cap);
+  H->B[1] = c.take<double>((size_t)npad * H->k_cap);
+  H->Z = c.take<double>((size_t)npad * H->k_cap);
+  H->part = c.take<double>((size_t)H->ch.nchunks * npad * H->k_cap);
+  H->gram_part = c.take<double>((size_t)H->nsl * 3 * H->k_cap * H->k_cap);
+  H->small = c.take<double>(SL::TOTAL);
+  H->V[0] = c.take<double>((size_t)npad * KMAX);
+  H->V[1] = c.take<double>((size_t)npad * KMAX);
+  H->fac_part = c.take<double>((size_t)std::max(H->nsl, 1) * FAC_STRIDE);
+  H->y = c.take<double>(H->rows);
+  H->y_old = c.take<double>(H->rows);
+  H->MX = c.take<double>(H->rows);
+  H->MX_old = c.take<double>(H->rows);
+  H->row_part = c.take<double>((size_t)H->nrow_blocks * ROW_PART);
+  H->pat_part = c.take<double>((size_t)H->npat_blocks * PAT_PART);
+  H->dval = c.take<double>(h.pat_a.size());
+  H->ring = c.take<IterRecord>(RING);
+  // problem data
+  DevProblem& d = H->dp;
+  d.pat_a = c.take<int>(h.pat_a.size());
+  d.pat_b = c.take<int>(h.pat_b.size());
+  d.pat_c = c.take<double>(h.pat_c.size());
+  d.pat_rptr = c.take<int>(h.pat_rptr.size());
+  d.pat_row = c.take<int>(h.pat_row.size());
+  d.pat_val = c.take<double>(h.pat_val.size());
+  d.row_ptr = c.take<int>(h.row_ptr.size());
+  d.row_a = c.take<int>(h.row_a.size());
+  d.row_b = c.take<int>(h.row_b.size());
+  d.row_w = c.take<double>(h.row_w.size());
+  d.sym_ptr = c.take<int>(h.sym_ptr.size());
+  d.sym_e = c.take<int>(h.sym_e.size());
+  d.tile_ptr = c.take<int>(h.tile_ptr.size());
+  d.tile_item = c.take<int>(h.tile_item.size());
+  d.tile_e = c.take<int>(h.tile_e.size());
+  d.r1_u = c.take<double>(h.r1_u.size());
+  d.row_r1 = c.take<int>(h.row_r1.size());
+  d.rhs = c.take<double>(h.rhs.size());
+  return c.off + 256;
+}
+
+static void setup_dims(proxsdp_handle* H) {
+  const Host& h = H->h;
+  H->n = h.n;
+  H->npad = h.npad;
+  H->rows = h.rows;
+  H->full = H->opt.full_eig || h.n <= KMAX;
+  if (H->full) {
+    H->r_cap = h.n;
+    H->k_cap = 16;
+  } else {
+    const int rmax_auto = 48;
+    H->r_cap = std::min(h.n, H->opt.r_max > 0 ? std::min(H->opt.r_max, rmax_auto) : rmax_auto);
+    H->k_cap = H->opt.block ? H->opt.block : k_for_r(H->r_cap);
+    H->k_cap = std::max(H->k_cap, 16);
+  }
+  if (H->opt.full_eig)
+    H->r = h.n;
+  else
+    H->r = std::min(std::max(H->opt.r0, 1), H->r_cap);
+  H->k = H->full ? 16 : (H->opt.block ? H->opt.block : k_for_r(H->r));
+  H->ch = chunking(h.npad);
+  H->nsl = n_slices(h.npad);
+  H->nrow_blocks = (h.rows + 255) / 256;
+  H->npat_blocks = std::min(1024, (h.n + 3) / 4);
+}
+
+static void fill_dev_problem(proxsdp_handle* H) {
+  const Host& h = H->h;
+  DevProblem& d = H->dp;
+  d.n = h.n;
+  d.npad = h.npad;
+  d.rows = h.rows;
+  d.m = h.m;
+  d.p = h.p;
+  d.n_pat = (int)h.pat_a.size();
+  d.tiles_side = h.npad / TILE;
+  d.n_r1 = h.n_r1;
+  for (int q = 0; q < MAX_R1; ++q) {
+    d.r1_row[q] = q < h.n_r1 ? h.r1_row[q] : 0;
+    d.r1_sigma[q] = q < h.n_r1 ? h.r1_sigma[q] : 0.0;
+    d.r1_norm2[q] = h.r1_norm2[q];
+  }
+  for (int t = 0; t < MAX_R1 * MAX_R1; ++t) d.r1_gram[t] = h.r1_gram[t];
+}
+
+template <class T>
+static int up(const T* dst, const std::vector<T>& src, hipStream_t st) {
+  if (src.empty()) return PROXSDP_OK;
+  HIP_OK(hipMemcpyAsync(const_cast<T*>(dst), src.data(), src.size() * sizeof(T),
+                        hipMemcpyHostToDevice, st));
+  return PROXSDP_OK;
+}
+
+static void zero(double* x, size_t count, hipStream_t st) {
+  if (!count) return;
+  const int64_t c = (int64_t)count;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((c + 255) / 256)), dim3(256), 0, st, x, c);
+}
+
+static int set_lds_limits() {
+  static bool done = false;
+  if (done) return PROXSDP_OK;
+  const int big = 160 * 1024;
+  HIP_OK(hipFuncSetAttribute((const void*)k_reduce_gram, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIP_OK(hipFuncSetAttribute((const void*)k_small_rr, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIP_OK(hipFuncSetAttribute((const void*)k_rowwise, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIP_OK(hipFuncSetAttribute((const void*)k_full_eig, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIP_OK(hipFuncSetAttribute((const void*)k_write_w, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  done = true;
+  return PROXSDP_OK;
+}
+
+// ----------------------------------------------------------- launch helpers
+static void launch_block(const double* W, int64_t ld, int n, int npad, const double* B, int k,
+                         double* part, const Chunking& ch, bool padded, hipStream_t st) {
+  dim3 grid(npad / 64, ch.nchunks);
+#define BP(KB)                                                                                   \
+  if (padded)                                                                                    \
+    hipLaunchKernelGGL((k_block_partial_f64<KB, true>), grid, dim3(256), 0, st, W, ld, n, B, k, \
+                       part, ch.rows_per_chunk, npad);                                           \
+  else                                                                                           \
+    hipLaunchKernelGGL((k_block_partial_f64<KB, false>), grid, dim3(256), 0, st, W, ld, n, B, k, \
+                       part, ch.rows_per_chunk, npad);
+  switch (k / 16) {
+    case 1: BP(1); break;
+    case 2: BP(2); break;
+    case 3: BP(3); break;
+    case 4: BP(4); break;
+    default: break;
+  }
+#undef BP
+}
+
+static void launch_reduce(const double* part, int nchunks, double* Z, const double* B,
+                          const double* Bprev, int npad, int k, double* gram_part, int cheb,
+                          double cc, double ce, bool grams, hipStream_t st) {
+  const size_t lds = 2 * (size_t)SLICE * k * sizeof(double);
+  hipLaunchKernelGGL(k_reduce_gram, dim3(n_slices(npad)), dim3(256), lds, st, part, nchunks, Z, B,
+                     Bprev, npad, k, gram_part, cheb, cc, ce, grams ? 1 : 0);
+}
+
+static void launch_rr(const double* gram_part, int nsl, double* small, int k, int r, int lam_off,
+                      int filter, hipStream_t st) {
+  const size_t lds = (3 * (size_t)k * k + 2 * KMAX + 3 * (KMAX / 2 + 1)) * sizeof(double) +
+                     (KMAX + 4) * sizeof(int);
+  hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(512), lds, st, gram_part, nsl, small, k, r, lam_off,
+                     filter);
+}
+
+static void launch_rowwise(proxsdp_handle* H, const double* B, double* V, int r, const double* Vold,
+                           int r_old, double* Bn, hipStream_t st) {
+  const size_t lds = (2 * (size_t)SLICE * H->k + 2 * (size_t)SLICE * std::max(r, 1)) * sizeof(double);
+  hipLaunchKernelGGL(k_rowwise, dim3(H->nsl), dim3(256), lds, st, B, H->Z, H->small, H->k, V, r,
+                     Vold, r_old, Bn, H->dp.n_r1, H->dp.r1_u, H->npad, H->fac_part);
+}
+
+static void launch_full(proxsdp_handle* H, double* V, int r, const double* Vold, int r_old,
+                        int lam_off) {
+  const int n = H->n;
+  const size_t lds = (2 * (size_t)n * n + n + 3 * (KMAX / 2 + 1)) * sizeof(double) +
+                     (KMAX + 4) * sizeof(int);
+  hipLaunchKernelGGL(k_full_eig, dim3(1), dim3(1024), lds, H->st, H->W, (int64_t)H->npad, n, V, r,
+                     Vold, r_old, H->small, lam_off, H->dp.n_r1, H->dp.r1_u, H->npad, H->fac_part);
+}
+
+static void launch_write(proxsdp_handle* H, double* Wout, int64_t ld, const double* V, int r,
+                         int lam_off, bool sparse, bool rank1, const FinArgs* fin) {
+  const int ts = H->npad / TILE;
+  const int rr = r + (rank1 ? H->dp.n_r1 : 0);
+  const size_t lds = ((size_t)TILE * (TILE + 1) + 2 * (size_t)TILE * std::max(rr, 1)) * sizeof(double);
+  FinArgs f{};
+  if (fin) f = *fin;
+  hipLaunchKernelGGL(k_write_w, dim3(ts * ts + (fin ? 1 : 0)), dim3(256), lds, H->st, Wout, ld,
+                     H->n, V, KMAX, r, H->small, lam_off, H->dp, H->y, H->y_old, H->dval,
+                     sparse ? 1 : 0, rank1 ? 1 : 0, fin ? 1 : 0, f, ts);
+}
+
+static int lam_slot(int parity) { return SL::LAM + parity * KMAX; }
+
+// Reduces the residual partials of the last row-wise call and reads the
+// largest relative Ritz residual of the kept pairs (synchronises).
+static int true_maxres(proxsdp_handle* H, int r, double* out) {
+  hipLaunchKernelGGL(k_reduce_res, dim3(1), dim3(256), 0, H->st, H->fac_part, H->nsl, r, H->small);
+  HIP_OK(hipMemcpyAsync(out, H->small + SL::SC + S_MAXRES, sizeof(double), hipMemcpyDeviceToHost, H->st));
+  HIP_OK(hipStreamSynchronize(H->st));
+  return PROXSDP_OK;
+}
+static int x2_slot(int parity) { return SL::SC + S_X2 + parity; }
+
+// Eigensolver rounds on the current W with the current basis.  `final_round`
+// forms the factors V[par] and the partials; other rounds only update the basis.
+static void eig_round(proxsdp_handle* H, int par, bool final_round) {
+  hipStream_t st = H->st;
+  const double* Bc = H->B[H->bcur];
+  double* Bn = H->B[1 - H->bcur];
+  prof_mark(H, H->ev_pass, H->n_pass, true);
+  launch_block(H->W, H->npad, H->n, H->npad, Bc, H->k, H->part, H->ch, true, st);
+  prof_mark(H, H->ev_pass, H->n_pass, false);
+  launch_reduce(H->part, H->ch.nchunks, H->Z, Bc, nullptr, H->npad, H->k, H->gram_part, 0, 0.0,
+                1.0, true, st);
+  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, st);
+  if (final_round)
+    launch_rowwise(H, Bc, H->V[par], H->r, H->V[1 - par], H->r_old, Bn, st);
+  else
+    launch_rowwise(H, Bc, nullptr, H->r, nullptr, 0, Bn, st);
+  H->bcur = 1 - H->bcur;
+  H->passes += 1;
+}
+
+static void pattern_and_write(proxsdp_handle* H, int par, int ring_slot) {
+  hipStream_t st = H->st;
+  hipLaunchKernelGGL(k_pattern, dim3(H->npat_blocks), dim3(256), 0, st, H->dp, H->V[par], H->r,
+                     H->small, lam_slot(par), H->y, H->y_old, H->dval, H->pat_part, 1);
+  FinArgs f{};
+  f.fac_part = H->fac_part;
+  f.nslices = H->full ? 1 : H->nsl;
+  f.r = H->r;
+  f.r_old = H->r_old;
+  f.lam_new = lam_slot(par);
+  f.lam_old = lam_slot(1 - par);
+  f.x2_new = S_X2 + par;
+  f.x2_old = S_X2 + (1 - par);
+  f.row_part = H->row_part;
+  f.nrow_blocks = H->nrow_blocks;
+  f.pat_part = H->pat_part;
+  f.npat_blocks = H->npat_blocks;
+  f.ring = H->ring;
+  f.ring_slot = ring_slot;
+  prof_mark(H, H->ev_write, H->n_write, true);
+  launch_write(H, H->W, H->npad, H->V[par], H->r, lam_slot(par), true, true, &f);
+  prof_mark(H, H->ev_write, H->n_write, false);
+}
+
+// One PDHG iteration (Algorithm 1 / Algorithm 2 inner loop).
+static void iterate_once(proxsdp_handle* H) {
+  hipStream_t st = H->st;
+  const int par = H->iters & 1;
+  // primal step: factors of aproj(W, r)
+  if (H->full) {
+    launch_full(H, H->V[par], H->r, H->V[1 - par], H->r_old, lam_slot(par));
+    H->passes += 1;
+  } else if (H->opt.eig_strict) {
+    // rounds until the kept Ritz pairs meet eig_tol, then one final round
+    for (int rd = 0; rd < 200; ++rd) {
+      eig_round(H, par, false);
+      double mr = 1.0;
+      if (true_maxres(H, H->r, &mr)) break;
+      if (mr <= H->opt.eig_tol) break;
+    }
+    eig_round(H, par, true);
+  } else {
+    for (int rd = 0; rd < H->m_rounds; ++rd) eig_round(H, par, rd == H->m_rounds - 1);
+  }
+  // dual step
+  hipLaunchKernelGGL(k_gather_dual, dim3(H->nrow_blocks), dim3(256), 0, st, H->dp, H->V[par],
+                     H->r, H->small, lam_slot(par), H->fac_part, H->full ? 1 : H->nsl, H->r_old,
+                     H->y, H->y_old, H->MX, H->MX_old, H->row_part);
+  // next W, residuals
+  pattern_and_write(H, par, H->iters % RING);
+  H->r_old = H->r;
+  H->iters += 1;
+}
+
+static void set_rank(proxsdp_handle* H, int r_new) {
+  if (r_new == H->r) return;
+  H->r = r_new;
+  H->rank_updates += 1;
+  if (H->full) return;
+  const int k_new = H->opt.block ? H->opt.block : k_for_r(r_new);
+  if (k_new != H->k) {
+    // re-layout the basis with the new width: old columns kept, new ones random
+    const int64_t cnt = (int64_t)H->npad * k_new;
+    hipLaunchKernelGGL(k_fill_basis, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, H->st,
+                       H->B[1 - H->bcur], k_new, H->B[H->bcur], H->k, std::min(H->k, k_new), H->n,
+                       H->npad, (uint32_t)(H->opt.seed * 7919 + H->rank_updates));
+    H->bcur = 1 - H->bcur;
+    H->k = k_new;
+  }
+}
+
+static int read_records(proxsdp_handle* H, int first_iter, int count, std::vector<IterRecord>& out) {
+  out.resize(count);
+  int done = 0;
+  while (done < count) {
+    const int slot = (first_iter + done) % RING;
+    const int len = std::min(count - done, RING - slot);
+    HIP_OK(hipMemcpyAsync(&out[done], H->ring + slot, len * sizeof(IterRecord),
+                          hipMemcpyDeviceToHost, H->st));
+    done += len;
+  }
+  return PROXSDP_OK;
+}
+
+static int fill_info(proxsdp_handle* H, const IterRecord& rec, double nonfinite) {
+  proxsdp_info& I = H->last;
+  I.status = H->status;
+  I.iters = H->iters;
+  I.r = H->r;
+  I.k = H->full ? H->n : H->k;
+  I.rank_updates = H->rank_updates;
+  I.passes = H->passes;
+  I.lambda_r = rec.lambda_r;
+  I.lambda_r1 = rec.lambda_r1;
+  I.eps_p = rec.eps_p;
+  I.eps_d = rec.eps_d;
+  I.rho_p = rec.eps_p / (1.0 + H->h.norm_c);
+  I.rho_d = rec.eps_d / (1.0 + H->h.norm_rhs);
+  I.obj = rec.obj;
+  I.dual_obj = rec.dual_obj;
+  I.alpha = H->opt.alpha;
+  I.norm_M = H->h.norm_m;
+  I.ritz_res = rec.maxres;
+  I.time_s = H->time_s;
+  (void)nonfinite;
+  return PROXSDP_OK;
+}
+
+// Control check after iteration H->iters (a multiple of check_every).
+static int control(proxsdp_handle* H) {
+  const int ce = H->opt.check_every;
+  std::vector<IterRecord> recs;
+  int rc = read_records(H, H->iters - ce, ce, recs);
+  if (rc) return rc;
+  double nonfinite = 0;
+  HIP_OK(hipMemcpyAsync(&nonfinite, H->small + SL::SC + S_NONFINITE, sizeof(double),
+                        hipMemcpyDeviceToHost, H->st));
+  HIP_OK(hipStreamSynchronize(H->st));
+  const IterRecord& rec = recs.back();
+  const double rho_p = rec.eps_p / (1.0 + H->h.norm_c);
+  const double rho_d = rec.eps_d / (1.0 + H->h.norm_rhs);
+  const double comb = rec.eps_p + rec.eps_d;
+  const int L = H->opt.window / ce;
+  if (nonfinite != 0.0 || !std::isfinite(comb)) {
+    H->status = PROXSDP_STATUS_NUMERICAL;
+  } else if (std::max(rho_p, rho_d) <= H->opt.tol) {
+    const int n = H->n;
+    if (H->r >= n || (double)(n - H->r) * std::max(rec.lambda_r, 0.0) <= H->eps_lambda) {
+      H->status = PROXSDP_STATUS_CONVERGED;
+    } else if (H->r >= H->r_cap) {
+      H->hist.push_back(comb);
+    } else {
+      set_rank(H, std::min(2 * H->r, H->r_cap));
+      H->hist.clear();
+    }
+  } else {
+    H->hist.push_back(comb);
+    if (H->r < H->r_cap && (int)H->hist.size() > L &&
+        H->hist.back() >= H->hist[H->hist.size() - 1 - L]) {
+      set_rank(H, std::min(2 * H->r, H->r_cap));
+      H->hist.clear();
+    }
+  }
+  // accuracy schedule of the partial eigensolve: relative Ritz residual target
+  // tied to the current residual level (summable errors, Section 3.2)
+  if (!H->full) {
+    const double eta = std::max(H->opt.eig_tol, 0.05 * std::max(rho_p, rho_d));
+    double worst = 0;
+    for (auto& x : recs) worst = std::max(worst, x.maxres);
+    if (worst > eta && H->m_rounds < H->opt.max_passes) H->m_rounds += 1;
+    else if (worst < 0.05 * eta && H->m_rounds > 1) H->m_rounds -= 1;
+  }
+  fill_info(H, rec, nonfinite);
+  return PROXSDP_OK;
+}
+
+static int warm_start(proxsdp_handle* H) {
+  // subspace for the first projection: random basis, rounds until the kept
+  // Ritz pairs are accurate to 1e-3 (relative) or 60 rounds.
+  if (H->full) return PROXSDP_OK;
+  const int64_t cnt = (int64_t)H->npad * H->k;
+  hipLaunchKernelGGL(k_fill_basis, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, H->st,
+                     H->B[H->bcur], H->k, nullptr, 0, 0, H->n, H->npad, (uint32_t)H->opt.seed);
+  for (int rd = 0; rd < 60; ++rd) {
+    eig_round(H, 0, false);
+    if (rd % 4 == 3) {
+      double mr = 1;
+      const int rc = true_maxres(H, H->r, &mr);
+      if (rc) return rc;
+      if (mr <= 1e-3) break;
+    }
+  }
+  return PROXSDP_OK;
+}
+
+static int init_state(proxsdp_handle* H) {
+  hipStream_t st = H->st;
+  // state: X0 = 0, y0 = 0
+  zero(H->W, (size_t)H->npad * H->npad, st);
+  zero(H->B[0], (size_t)H->npad * H->k_cap, st);
+  zero(H->B[1], (size_t)H->npad * H->k_cap, st);
+  zero(H->Z, (size_t)H->npad * H->k_cap, st);
+  zero(H->small, SL::TOTAL, st);
+  zero(H->V[0], (size_t)H->npad * KMAX, st);
+  zero(H->V[1], (size_t)H->npad * KMAX, st);
+  zero(H->fac_part, (size_t)std::max(H->nsl, 1) * FAC_STRIDE, st);
+  zero(H->y, H->rows, st);
+  zero(H->y_old, H->rows, st);
+  zero(H->MX, H->rows, st);
+  zero(H->MX_old, H->rows, st);
+  zero(H->row_part, (size_t)H->nrow_blocks * ROW_PART, st);
+  zero(H->pat_part, (size_t)H->npat_blocks * PAT_PART, st);
+  std::vector<double> sc(S_COUNT, 0.0);
+  sc[S_ALPHA] = H->opt.alpha;
+  HIP_OK(hipMemcpyAsync(H->small + SL::SC, sc.data(), sc.size() * sizeof(double),
+                        hipMemcpyHostToDevice, st));
+  H->iters = 0;
+  H->passes = 0;
+  H->rank_updates = 0;
+  H->m_rounds = 2;
+  H->status = PROXSDP_STATUS_RUNNING;
+  H->hist.clear();
+  H->time_s = 0;
+  H->last = proxsdp_info{};
+  H->bcur = 0;
+  H->r_old = 0;
+  H->r = H->opt.full_eig ? H->n : std::min(std::max(H->opt.r0, 1), H->r_cap);
+  H->k = H->full ? 16 : (H->opt.block ? H->opt.block : k_for_r(H->r));
+  // W0 = X0 - alpha (C - M*(y0)) = -alpha C
+  const int r_save = H->r;
+  H->r = 0;
+  pattern_and_write(H, 1, RING - 1);
+  H->r = r_save;
+  const double zero_flag = 0.0;
+  HIP_OK(hipMemcpyAsync(H->small + SL::SC + S_NONFINITE, &zero_flag, sizeof(double),
+                        hipMemcpyHostToDevice, st));
+  int rc = warm_start(H);
+  if (rc) return rc;
+  HIP_OK(hipStreamSynchronize(st));
+  return PROXSDP_OK;
+}
+
+// ======================================================================== API
+extern "C" {
+
+int proxsdp_default_options(proxsdp_options* o) {
+  if (!o) return fail(PROXSDP_ERR_INVALID, "options is NULL");
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-4;
+  o->eps_lambda = -1.0;
+  o->alpha = 0.0;
+  o->window = 50;
+  o->check_every = 10;
+  o->r0 = 1;
+  o->r_max = 0;
+  o->full_eig = 0;
+  o->precision = PROXSDP_FP64;
+  o->max_iters = 200000;
+  o->time_limit_s = 1200.0;
+  o->row_scaling = 1;
+  o->block = 0;
+  o->eig_tol = 1e-10;
+  o->max_passes = 8;
+  o->seed = 1;
+  return PROXSDP_OK;
+}
+
+int proxsdp_workspace_size(const proxsdp_problem* pb, const proxsdp_options* opt, size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(PROXSDP_ERR_INVALID, "bytes is NULL");
+  proxsdp_options o;
+  if (opt) o = *opt; else proxsdp_default_options(&o);
+  int rc = validate(pb, &o);
+  if (rc) return rc;
+  proxsdp_handle H;
+  H.opt = o;
+  rc = preprocess(pb, o.row_scaling, H.h);
+  if (rc) return rc;
+  setup_dims(&H);
+  *bytes = carve(&H, nullptr);
+  return PROXSDP_OK;
+}
+
+int proxsdp_create(const proxsdp_problem* pb, const proxsdp_options* opt, void* ws, size_t ws_bytes,
+                   void* stream, proxsdp_handle** out) {
+  g_err.clear();
+  if (!out) return fail(PROXSDP_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  proxsdp_options o;
+  if (opt) o = *opt; else proxsdp_default_options(&o);
+  int rc = validate(pb, &o);
+  if (rc) return rc;
+  if (!ws) return fail(PROXSDP_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PROXSDP_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  auto* H = new proxsdp_handle();
+  H->opt = o;
+  H->st = static_cast<hipStream_t>(stream);
+  rc = preprocess(pb, o.row_scaling, H->h);
+  if (rc) { delete H; return rc; }
+  setup_dims(H);
+  const size_t need = carve(H, nullptr);
+  if (ws_bytes < need) {
+    delete H;
+    return fail(PROXSDP_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  }
+  carve(H, ws);
+  fill_dev_problem(H);
+  if ((rc = set_lds_limits())) { delete H; return rc; }
+  const Host& h = H->h;
+  H->opt.alpha = (o.alpha > 0) ? o.alpha : 0.95 / h.norm_m;
+  H->eps_lambda = (o.eps_lambda >= 0) ? o.eps_lambda : o.tol;
+  hipStream_t st = H->st;
+  const DevProblem& d = H->dp;
+#define UP(dst, src) if ((rc = up(dst, src, st))) { delete H; return rc; }
+  UP(d.pat_a, h.pat_a); UP(d.pat_b, h.pat_b); UP(d.pat_c, h.pat_c);
+  UP(d.pat_rptr, h.pat_rptr); UP(d.pat_row, h.pat_row); UP(d.pat_val, h.pat_val);
+  UP(d.row_ptr, h.row_ptr); UP(d.row_a, h.row_a); UP(d.row_b, h.row_b); UP(d.row_w, h.row_w);
+  UP(d.sym_ptr, h.sym_ptr); UP(d.sym_e, h.sym_e);
+  UP(d.tile_ptr, h.tile_ptr); UP(d.tile_item, h.tile_item); UP(d.tile_e, h.tile_e);
+  UP(d.r1_u, h.r1_u); UP(d.row_r1, h.row_r1); UP(d.rhs, h.rhs);
+#undef UP
+  if ((rc = init_state(H))) { delete H; return rc; }
+  H->ws_need = need;
+  H->status = PROXSDP_STATUS_RUNNING;
+  *out = H;
+  return PROXSDP_OK;
+}
+
+int proxsdp_step(proxsdp_handle* H, int32_t n_iters, proxsdp_info* info) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  if (n_iters < 0) return fail(PROXSDP_ERR_INVALID, "n_iters < 0");
+  auto t_last = std::chrono::steady_clock::now();
+  auto tick = [&]() {
+    const auto now = std::chrono::steady_clock::now();
+    H->time_s += std::chrono::duration<double>(now - t_last).count();
+    t_last = now;
+  };
+  for (int t = 0; t < n_iters && H->status == PROXSDP_STATUS_RUNNING; ++t) {
+    iterate_once(H);
+    if (H->iters % H->opt.check_every == 0) {
+      const int rc = control(H);  // synchronises the stream
+      if (rc) return rc;
+      tick();
+      H->last.time_s = H->time_s;
+      if (H->status == PROXSDP_STATUS_RUNNING && H->iters >= H->opt.max_iters)
+        H->status = PROXSDP_STATUS_MAX_ITERS;
+      if (H->status == PROXSDP_STATUS_RUNNING && H->opt.time_limit_s > 0 &&
+          H->time_s > H->opt.time_limit_s)
+        H->status = PROXSDP_STATUS_TIME_LIMIT;
+      H->last.status = H->status;
+    }
+  }
+  if (info) {
+    HIP_OK(hipStreamSynchronize(H->st));
+    if (H->iters > 0 && H->iters % H->opt.check_every != 0) {
+      std::vector<IterRecord> recs;
+      int rc = read_records(H, H->iters - 1, 1, recs);
+      if (rc) return rc;
+      HIP_OK(hipStreamSynchronize(H->st));
+      fill_info(H, recs.back(), 0.0);
+    }
+    tick();
+    H->last.status = H->status;
+    H->last.time_s = H->time_s;
+    *info = H->last;
+  } else {
+    tick();
+  }
+  return PROXSDP_OK;
+}
+
+int proxsdp_solve(proxsdp_handle* H, proxsdp_info* info) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  while (H->status == PROXSDP_STATUS_RUNNING) {
+    const int rc = proxsdp_step(H, H->opt.check_every, nullptr);
+    if (rc) return rc;
+  }
+  HIP_OK(hipStreamSynchronize(H->st));
+  if (info) {
+    H->last.status = H->status;
+    H->last.time_s = H->time_s;
+    *info = H->last;
+  }
+  return PROXSDP_OK;
+}
+
+int proxsdp_get_factors(proxsdp_handle* H, double* V, double* lambda, int32_t* r_out) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  const int par = (H->iters - 1) & 1;
+  const int r = H->iters > 0 ? H->r_old : 0;
+  if (r_out) *r_out = r;
+  if (H->iters == 0) return PROXSDP_OK;
+  if (V) {
+    std::vector<double> tmp((size_t)H->n * KMAX);
+    HIP_OK(hipMemcpyAsync(tmp.data(), H->V[par], tmp.size() * sizeof(double), hipMemcpyDeviceToHost, H->st));
+    HIP_OK(hipStreamSynchronize(H->st));
+    for (int i = 0; i < H->n; ++i)
+      for (int t = 0; t < r; ++t) V[(size_t)i * r + t] = tmp[(size_t)i * KMAX + t];
+  }
+  if (lambda) {
+    HIP_OK(hipMemcpyAsync(lambda, H->small + lam_slot(par), r * sizeof(double), hipMemcpyDeviceToHost, H->st));
+    HIP_OK(hipStreamSynchronize(H->st));
+  }
+  return PROXSDP_OK;
+}
+
+int proxsdp_get_solution(proxsdp_handle* H, double* X, double* y, int32_t on_device) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  const int n = H->n;
+  if (y) {
+    std::vector<double> ys(H->rows);
+    HIP_OK(hipMemcpyAsync(ys.data(), H->y, H->rows * sizeof(double), hipMemcpyDeviceToHost, H->st));
+    HIP_OK(hipStreamSynchronize(H->st));
+    for (int i = 0; i < H->rows; ++i) ys[i] /= H->h.scale[i];
+    if (on_device)
+      HIP_OK(hipMemcpyAsync(y, ys.data(), H->rows * sizeof(double), hipMemcpyHostToDevice, H->st));
+    else
+      std::memcpy(y, ys.data(), H->rows * sizeof(double));
+  }
+  if (X) {
+    const int par = (H->iters - 1) & 1;
+    const int r = H->iters > 0 ? H->r_old : 0;
+    if (on_device) {
+      launch_write(H, X, n, H->V[par], r, lam_slot(par), false, false, nullptr);
+    } else {
+      std::vector<double> V((size_t)n * std::max(r, 1)), lam(std::max(r, 1));
+      int32_t rr = 0;
+      const int rc = proxsdp_get_factors(H, V.data(), lam.data(), &rr);
+      if (rc) return rc;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          double acc = 0;
+          for (int t = 0; t < rr; ++t) acc += lam[t] * V[(size_t)i * rr + t] * V[(size_t)j * rr + t];
+          X[(size_t)i * n + j] = acc;
+        }
+    }
+  }
+  HIP_OK(hipStreamSynchronize(H->st));
+  return PROXSDP_OK;
+}
+
+// --------------------------------------------------------- projection only
+// Context of one stateless projection: the solver's buffers with an empty
+// constraint set.
+static size_t project_layout(proxsdp_handle* H, int n, int r, void* ws, double** gpart) {
+  H->n = n;
+  H->npad = roundup(n, TILE);
+  H->rows = 0;
+  H->full = (n <= KMAX);
+  H->r = r;
+  H->k = H->full ? 16 : k_for_r(r);
+  H->k_cap = H->k;
+  H->ch = chunking(H->npad);
+  H->nsl = n_slices(H->npad);
+  Carver c(ws);
+  const int npad = H->npad;
+  H->B[0] = c.take<double>((size_t)npad * H->k);
+  H->B[1] = c.take<double>((size_t)npad * H->k);
+  H->Z = c.take<double>((size_t)npad * H->k);
+  H->part = c.take<double>((size_t)H->ch.nchunks * npad * H->k);
+  H->gram_part = c.take<double>((size_t)H->nsl * 3 * H->k * H->k);
+  H->small = c.take<double>(SL::TOTAL);
+  H->V[0] = c.take<double>((size_t)npad * KMAX);
+  H->V[1] = H->V[0];
+  H->fac_part = c.take<double>((size_t)std::max(H->nsl, 1) * FAC_STRIDE);
+  *gpart = c.take<double>(256);
+  return c.off + 256;
+}
+
+int proxsdp_project_workspace_size(int32_t n, int32_t r, int32_t precision, size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(PROXSDP_ERR_INVALID, "bytes is NULL");
+  if (n < 1) return fail(PROXSDP_ERR_INVALID, "n must be >= 1");
+  if (r < 0) return fail(PROXSDP_ERR_INVALID, "r must be >= 0");
+  if (precision != PROXSDP_FP64) return fail(PROXSDP_ERR_UNSUPPORTED, "only PROXSDP_FP64 is built");
+  const int re = (r == 0 || r >= n) ? n : r;
+  if (n > KMAX && re > 48)
+    return fail(PROXSDP_ERR_UNSUPPORTED, "for n > 64 the target rank must be <= 48");
+  proxsdp_handle H;
+  double* g = nullptr;
+  *bytes = project_layout(&H, n, re, nullptr, &g);
+  return PROXSDP_OK;
+}
+
+int proxsdp_project_psd(const void* S, int32_t n, int64_t lds, int32_t r, int32_t precision,
+                        double tol, void* P, int64_t ldp, double* evals, double* evecs,
+                        int32_t* rank_out, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!S) return fail(PROXSDP_ERR_INVALID, "S is NULL");
+  if (n < 1 || lds < n) return fail(PROXSDP_ERR_INVALID, "need n >= 1 and lds >= n");
+  if (P && ldp < n) return fail(PROXSDP_ERR_INVALID, "ldp < n");
+  size_t need = 0;
+  int rc = proxsdp_project_workspace_size(n, r, precision, &need);
+  if (rc) return rc;
+  if (!ws) return fail(PROXSDP_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PROXSDP_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < need) return fail(PROXSDP_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  if ((rc = set_lds_limits())) return rc;
+  if (!(tol > 0)) tol = 1e-12;
+  const int re = (r == 0 || r >= n) ? n : r;
+  proxsdp_handle H;
+  H.st = static_cast<hipStream_t>(stream);
+  double* gpart = nullptr;
+  project_layout(&H, n, re, ws, &gpart);
+  H.dp.n = n;
+  H.dp.npad = H.npad;
+  H.dp.tiles_side = H.npad / TILE;
+  hipStream_t st = H.st;
+  zero(H.small, SL::TOTAL, st);
+  zero(H.V[0], (size_t)H.npad * KMAX, st);
+  const double* Sd = static_cast<const double*>(S);
+  const int lam_off = lam_slot(0);
+  if (H.full) {
+    const size_t lds_b = (2 * (size_t)n * n + n + 3 * (KMAX / 2 + 1)) * sizeof(double) + (KMAX + 4) * sizeof(int);
+    hipLaunchKernelGGL(k_full_eig, dim3(1), dim3(1024), lds_b, st, Sd, lds, n, H.V[0], re, H.V[0], 0,
+                       H.small, lam_off, 0, (const double*)nullptr, H.npad, H.fac_part);
+  } else {
+    const int k = H.k;
+    const int64_t cnt = (int64_t)H.npad * k;
+    hipLaunchKernelGGL(k_fill_basis, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, H.B[0], k,
+                       (const double*)nullptr, 0, 0, n, H.npad, 12345u);
+    H.bcur = 0;
+    const int gblocks = std::min(256, (n + 3) / 4);
+    hipLaunchKernelGGL(k_gersh_dense, dim3(gblocks), dim3(256), 0, st, Sd, lds, n, gpart);
+    hipLaunchKernelGGL(k_reduce_min, dim3(1), dim3(256), 0, st, gpart, gblocks, H.small, (int)S_GERSH);
+    bool ok = false;
+    const int max_rounds = 600;
+    for (int rd = 0; rd < max_rounds; ++rd) {
+      const double* Bc = H.B[H.bcur];
+      double* Bn = H.B[1 - H.bcur];
+      launch_block(Sd, lds, n, H.npad, Bc, k, H.part, H.ch, false, st);
+      launch_reduce(H.part, H.ch.nchunks, H.Z, Bc, nullptr, H.npad, k, H.gram_part, 0, 0.0, 1.0, true, st);
+      const int n_unshifted = 6;
+      launch_rr(H.gram_part, H.nsl, H.small, k, re, lam_off, rd >= n_unshifted ? 1 : 0, st);
+      if (rd == n_unshifted - 1) hipLaunchKernelGGL(k_set_lower_bound, dim3(1), dim3(64), 0, st, H.small);
+      launch_rowwise(&H, Bc, H.V[0], re, H.V[0], 0, Bn, st);
+      const bool check = (rd % 4 == 3) || rd == max_rounds - 1;
+      if (check) {
+        double mr = 1.0;
+        if ((rc = true_maxres(&H, re, &mr))) return rc;
+        if (mr <= tol) { ok = true; break; }
+      }
+      H.bcur = 1 - H.bcur;
+    }
+    if (!ok) {
+      HIP_OK(hipStreamSynchronize(st));
+      return fail(PROXSDP_ERR_UNSUPPORTED, "partial eigensolve did not reach tol within the pass budget");
+    }
+  }
+  if (P) launch_write(&H, static_cast<double*>(P), ldp, H.V[0], re, lam_off, false, false, nullptr);
+  std::vector<double> theta(std::max(re, 1));
+  HIP_OK(hipMemcpyAsync(theta.data(), H.small + SL::THETA, re * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (evecs) {
+    std::vector<double> tmp((size_t)n * KMAX);
+    HIP_OK(hipMemcpyAsync(tmp.data(), H.V[0], tmp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i)
+      for (int t = 0; t < re; ++t) evecs[(size_t)i * re + t] = tmp[(size_t)i * KMAX + t];
+  }
+  HIP_OK(hipStreamSynchronize(st));
+  if (evals) std::memcpy(evals, theta.data(), re * sizeof(double));
+  if (rank_out) {
+    int c = 0;
+    for (int t = 0; t < re; ++t) c += theta[t] > 0.0;
+    *rank_out = c;
+  }
+  return PROXSDP_OK;
+}
+
+int proxsdp_reset(proxsdp_handle* H) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  return init_state(H);
+}
+
+int proxsdp_profile_enable(proxsdp_handle* H, int32_t enable) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  if (enable) {
+    while ((int)H->ev_pass.size() < 2 * PROF_MAX) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      H->ev_pass.push_back(e);
+    }
+    while ((int)H->ev_write.size() < 2 * PROF_MAX) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      H->ev_write.push_back(e);
+    }
+  }
+  H->prof = enable != 0;
+  H->n_pass = 0;
+  H->n_write = 0;
+  return PROXSDP_OK;
+}
+
+int proxsdp_profile_read(proxsdp_handle* H, double* pass_ms, int32_t* pass_count, double* write_ms,
+                         int32_t* write_count) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  HIP_OK(hipStreamSynchronize(H->st));
+  double tp = 0, tw = 0;
+  for (int i = 0; i < H->n_pass; ++i) {
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, H->ev_pass[2 * i], H->ev_pass[2 * i + 1]));
+    tp += ms;
+  }
+  for (int i = 0; i < H->n_write; ++i) {
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, H->ev_write[2 * i], H->ev_write[2 * i + 1]));
+    tw += ms;
+  }
+  if (pass_ms) *pass_ms = tp;
+  if (pass_count) *pass_count = H->n_pass;
+  if (write_ms) *write_ms = tw;
+  if (write_count) *write_count = H->n_write;
+  H->prof = false;
+  return PROXSDP_OK;
+}
+
+int proxsdp_debug_scalars(proxsdp_handle* H, double* out, int32_t count) {
+  g_err.clear();
+  if (!H || !out) return fail(PROXSDP_ERR_INVALID, "NULL argument");
+  const int c1 = std::min<int>(count, 64);
+  if (c1 > 0)
+    HIP_OK(hipMemcpyAsync(out, H->small + SL::SC, c1 * sizeof(double), hipMemcpyDeviceToHost, H->st));
+  if (count > 64) {
+    const int c2 = std::min<int>(count - 64, KMAX);
+    HIP_OK(hipMemcpyAsync(out + 64, H->small + SL::THETA, c2 * sizeof(double), hipMemcpyDeviceToHost, H->st));
+  }
+  HIP_OK(hipStreamSynchronize(H->st));
+  return PROXSDP_OK;
+}
+
+void proxsdp_destroy(proxsdp_handle* H) { delete H; }
+
+const char* proxsdp_last_error(void) { return g_err.c_str(); }
+
+const char* proxsdp_version(void) { return "proxsdp-mi355x 0.1 (gfx950, FP64)"; }
+
+}  // extern "C"

@@ -1,0 +1,440 @@
+// Single-workgroup kernels for the small dense problems of the partial
+// eigensolve (Rayleigh-Ritz on the k x k projected matrix) and for the exact
+// eigendecomposition used by PD-SDP at small n (Section 2.3.2).
+//
+// Eigensolver: cyclic two-sided Jacobi with the round-robin (tournament)
+// ordering, so that k/2 disjoint rotations are applied per round in
+// parallel; LDS resident.  Rotation angle from the 2x2 symmetric Schur
+// decomposition (Golub and Van Loan, Algorithm 8.4.1).
+#pragma once
+
+#include "common.hpp"
+
+namespace proxsdp {
+
+// Index of the partner pairs in round `rnd` of a kk-player round robin
+// (kk even): player 0 stays, the others rotate.
+__device__ inline int rr_player(int pos, int rnd, int kk) {
+  if (pos == 0) return 0;
+  return ((pos - 1 + rnd) % (kk - 1)) + 1;
+}
+
+// Symmetric eigendecomposition of A (k x k, LDS, stride lda) in place: on exit
+// the diagonal holds the eigenvalues and U (LDS, stride ldu) the eigenvectors
+// (columns).  `rot` is LDS scratch of 3 * (k/2 + 1) doubles + ints.
+// Returns the number of sweeps.
+__device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double* cs, int* flag,
+                          int max_sweeps) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int t = tid; t < k * k; t += nt) {
+    const int i = t / k, j = t - (t / k) * k;
+    U[i * ldu + j] = (i == j) ? 1.0 : 0.0;
+  }
+  const int kk = (k & 1) ? k + 1 : k;
+  const int np = kk / 2;
+  double* cc = cs;
+  double* ss = cs + np;
+  int* pp = reinterpret_cast<int*>(cs + 2 * np);
+  int* qq = pp + np;
+  int sweeps = 0;
+  __syncthreads();
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < kk - 1; ++rnd) {
+      for (int i = tid; i < np; i += nt) {
+        int p = rr_player(i, rnd, kk), q = rr_player(kk - 1 - i, rnd, kk);
+        if (p > q) { const int t = p; p = q; q = t; }
+        double c = 1.0, s = 0.0;
+        if (q < k) {
+          const double app = A[p * lda + p], aqq = A[q * lda + q], apq = A[p * lda + q];
+          const double thr = 1e-18 * sqrt(fabs(app * aqq)) + 1e-300;
+          if (fabs(apq) > thr) {
+            const double th = (aqq - app) / (2.0 * apq);
+            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+            *flag = 1;
+          }
+        }
+        cc[i] = c; ss[i] = s; pp[i] = p; qq[i] = (q < k) ? q : -1;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int t = tid; t < np * k; t += nt) {
+        const int i = t / k, j = t - (t / k) * k;
+        const int q = qq[i];
+        if (q < 0 || ss[i] == 0.0) continue;
+        const int p = pp[i];
+        const double c = cc[i], s = ss[i];
+        const double ap = A[p * lda + j], aq = A[q * lda + j];
+        A[p * lda + j] = c * ap - s * aq;
+        A[q * lda + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns: A <- A J, U <- U J
+      for (int t = tid; t < np * k; t += nt) {
+        const int i = t / k, j = t - (t / k) * k;
+        const int q = qq[i];
+        if (q < 0 || ss[i] == 0.0) continue;
+        const int p = pp[i];
+        const double c = cc[i], s = ss[i];
+        const double ap = A[j * lda + p], aq = A[j * lda + q];
+        A[j * lda + p] = c * ap - s * aq;
+        A[j * lda + q] = s * ap + c * aq;
+        const double up = U[j * ldu + p], uq = U[j * ldu + q];
+        U[j * ldu + p] = c * up - s * uq;
+        U[j * ldu + q] = s * up + c * uq;
+      }
+      __syncthreads();
+    }
+    ++sweeps;
+    const int any = *flag;
+    __syncthreads();
+    if (!any) break;
+  }
+  return sweeps;
+}
+
+// Sorts eigenvalues (diagonal of A) decreasingly: writes values to `vals`
+// and the permutation to `perm` (single thread; k <= KMAX).
+__device__ void sort_desc(const double* A, int lda, int k, double* vals, int* perm) {
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < k; ++i) { perm[i] = i; vals[i] = A[i * lda + i]; }
+    for (int i = 1; i < k; ++i) {
+      const double v = vals[i];
+      const int p = perm[i];
+      int j = i - 1;
+      while (j >= 0 && vals[j] < v) { vals[j + 1] = vals[j]; perm[j + 1] = perm[j]; --j; }
+      vals[j + 1] = v;
+      perm[j + 1] = p;
+    }
+  }
+  __syncthreads();
+}
+
+// Rayleigh-Ritz on span(B) from the reduced Grams G = B^T B, T = B^T W B,
+// P = (W B)^T (W B).  Generalised problem T s = theta G s through a Cholesky
+// factor of the column-equilibrated G (one CholeskyQR step folded into RR).
+// Writes (small): S (k x k, V = B S with V^T V = I), THETA (decreasing), RES
+// (relative Ritz residuals ||W v - theta v|| / max|theta|), lambda_+ of the r
+// kept pairs at lam_off, S_LAMR/S_LAMR1/S_MAXRES/S_NORMW, and the next-basis
+// coefficients MZ, MB of the degree-one Chebyshev filter
+//   Bn_i = (W - c I) v_i / ||(W - c I) v_i||,  c = (lo + theta_k) / 2,
+// where lo = small[S_GERSH] bounds the spectrum from below (filter != 0;
+// filter == 0 gives Bn_i = W v_i / ||W v_i||).
+// LDS: 3 k x k matrices (L, Tt, U) + vectors.
+__global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ gram_part,
+                                                  int nslices, double* __restrict__ small, int k,
+                                                  int r, int lam_off, int filter) {
+  extern __shared__ double sm[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int kk = k * k;
+  double* L = sm;                 // k x k
+  double* M = L + kk;             // k x k
+  double* U = M + kk;             // k x k
+  double* d = U + kk;             // k
+  double* vals = d + KMAX;        // k
+  double* cs = vals + KMAX;       // 3 * (KMAX/2 + 1)
+  int* perm = reinterpret_cast<int*>(cs + 3 * (KMAX / 2 + 1));
+  int* flag = perm + KMAX;  // [0] dropped count, [1] jacobi, [2] current column dropped
+  double* G = small + SL::GG;
+  double* T = small + SL::TG;
+  double* P = small + SL::PG;
+  // 1. reduce the slice partials (G, T, P contiguous per slice)
+  for (int t = tid; t < 3 * kk; t += nt) {
+    double acc = 0.0;
+    for (int s = 0; s < nslices; ++s) acc += gram_part[(int64_t)s * 3 * kk + t];
+    const int which = t / kk;
+    G[which * SL::kk + (t - which * kk)] = acc;  // slots GG, TG, PG (stride k inside)
+  }
+  __syncthreads();
+  __threadfence_block();
+  // 2. symmetrise, equilibrate: d_i = 1/sqrt(G_ii)
+  for (int t = tid; t < k; t += nt) {
+    const double g = G[t * k + t];
+    d[t] = (g > 0.0) ? 1.0 / sqrt(g) : 1.0;
+  }
+  __syncthreads();
+  for (int t = tid; t < kk; t += nt) {
+    const int i = t / k, j = t - (t / k) * k;
+    const double tij = 0.5 * (T[i * k + j] + T[j * k + i]);
+    const double gij = 0.5 * (G[i * k + j] + G[j * k + i]);
+    L[t] = gij * d[i] * d[j] + ((i == j) ? 1e-15 * k : 0.0);
+    M[t] = tij * d[i] * d[j];
+  }
+  if (tid == 0) { flag[0] = 0; flag[1] = 0; flag[2] = 0; }
+  __syncthreads();
+  // symmetrised T and P are written back for the residual step
+  for (int t = tid; t < kk; t += nt) {
+    const int i = t / k, j = t - (t / k) * k;
+    if (i < j) {
+      const double tij = 0.5 * (T[i * k + j] + T[j * k + i]);
+      const double pij = 0.5 * (P[i * k + j] + P[j * k + i]);
+      T[i * k + j] = tij; T[j * k + i] = tij;
+      P[i * k + j] = pij; P[j * k + i] = pij;
+    }
+  }
+  // 3. Cholesky of the equilibrated G (lower, in L).  A column whose pivot
+  //    falls below 1e-14 (numerically dependent on the previous ones) is
+  //    dropped: L_jj = 1 with a zero sub-column, so its orthogonalised
+  //    direction is the tiny remainder and its Ritz value is ~0.
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) {
+      const double piv = L[j * k + j];
+      if (!(piv > 1e-14)) {
+        L[j * k + j] = 1.0;
+        flag[0] += 1;
+        flag[2] = 1;
+      } else {
+        L[j * k + j] = sqrt(piv);
+        flag[2] = 0;
+      }
+    }
+    __syncthreads();
+    const double ljj = L[j * k + j];
+    const bool dropped = flag[2] != 0;
+    for (int i = j + 1 + tid; i < k; i += nt) L[i * k + j] = dropped ? 0.0 : L[i * k + j] / ljj;
+    __syncthreads();
+    for (int t = tid; t < kk; t += nt) {
+      const int i = t / k, c = t - (t / k) * k;
+      if (i > j && c > j && c <= i) L[i * k + c] -= L[i * k + j] * L[c * k + j];
+    }
+    __syncthreads();
+  }
+  // 4. Tt = L^{-1} M L^{-T}: U = L^{-1} M column by column, then M = L^{-1} U^T.
+  for (int c = tid; c < k; c += nt) {
+    for (int i = 0; i < k; ++i) {
+      double v = M[i * k + c];
+      for (int j = 0; j < i; ++j) v -= L[i * k + j] * U[j * k + c];
+      U[i * k + c] = v / L[i * k + i];
+    }
+  }
+  __syncthreads();
+  for (int c = tid; c < k; c += nt) {
+    for (int i = 0; i < k; ++i) {
+      double v = U[c * k + i];
+      for (int j = 0; j < i; ++j) v -= L[i * k + j] * M[j * k + c];
+      M[i * k + c] = v / L[i * k + i];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < kk; t += nt) {
+    const int i = t / k, j = t - (t / k) * k;
+    if (i < j) {
+      const double v = 0.5 * (M[i * k + j] + M[j * k + i]);
+      M[i * k + j] = v;
+      M[j * k + i] = v;
+    }
+  }
+  __syncthreads();
+  // 5. eigendecomposition of Tt
+  const int sweeps = jacobi_eig(M, k, U, k, k, cs, flag + 1, 40);
+  sort_desc(M, k, k, vals, perm);
+  // 6. S = D L^{-T} U_sorted: back substitution per column, written to small[S].
+  double* S = small + SL::S;
+  for (int c = tid; c < k; c += nt) {
+    const int pc = perm[c];
+    for (int i = k - 1; i >= 0; --i) {
+      double v = U[i * k + pc];
+      for (int j = i + 1; j < k; ++j) v -= L[j * k + i] * M[j * k + pc];
+      M[i * k + pc] = v / L[i * k + i];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < kk; t += nt) {
+    const int i = t / k, c = t - (t / k) * k;
+    S[i * KMAX + c] = d[i] * M[i * k + perm[c]];
+  }
+  __syncthreads();
+  __threadfence_block();
+  // 7. Ritz residuals and filter norms per column c (s = S[:, c], ||v|| = 1):
+  //    ||W v||^2 = s^T P s, v^T W v = s^T T s = theta,
+  //    ||(W - cI) v||^2 = s^T P s - 2 c s^T T s + c^2.
+  double* theta = small + SL::THETA;
+  double* res = small + SL::RES;
+  double scale = fmax(fabs(vals[0]), fabs(vals[k - 1]));
+  if (!(scale > 0.0)) scale = 1.0;
+  const double thk = vals[k - 1];
+  double fc = 0.0, fe = 1.0;
+  if (filter) {
+    double lo = small[SL::SC + S_GERSH];
+    if (!(lo < thk)) lo = thk - 0.5 * (vals[0] - thk) - 1e-300;
+    fc = 0.5 * (lo + thk);
+    fe = fmax(0.5 * (thk - lo), 1e-300);
+  }
+  for (int c = tid; c < k; c += nt) {
+    double sps = 0.0, sts = 0.0;
+    for (int i = 0; i < k; ++i) {
+      double pi = 0.0, ti = 0.0;
+      for (int j = 0; j < k; ++j) {
+        const double sj = S[j * KMAX + c];
+        pi += P[i * k + j] * sj;
+        ti += T[i * k + j] * sj;
+      }
+      const double si = S[i * KMAX + c];
+      sps += si * pi;
+      sts += si * ti;
+    }
+    const double th = vals[c];
+    theta[c] = th;
+    res[c] = sqrt(fmax(sps - th * th, 0.0)) / scale;
+    // column scale of the next basis: the predicted norm ||(W - cI) v||, floored
+    // at 1e-7 of the filter's largest amplification (the prediction cancels
+    // below that level), so that no column is blown up by rounding noise.
+    const double nrm2 = filter ? (sps - 2.0 * fc * sts + fc * fc) : sps;
+    const double gam = filter ? fmax(fabs(vals[0] - fc), fe) : scale;
+    const double inv = 1.0 / fmax(sqrt(fmax(nrm2, 0.0)), 1e-7 * gam);
+    for (int i = 0; i < k; ++i) {
+      const double si = S[i * KMAX + c];
+      small[SL::MZ + i * KMAX + c] = si * inv;
+      small[SL::MB + i * KMAX + c] = -fc * si * inv;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double mr = 0.0;
+    const int rk = r < k ? r : k;
+    int npos = 0;
+    while (npos < rk && vals[npos] > 0.0) ++npos;
+    const int nchk = npos > 0 ? npos : (rk > 0 ? 1 : 0);
+    for (int c = 0; c < nchk; ++c) mr = fmax(mr, res[c]);
+    for (int c = 0; c < rk; ++c) small[lam_off + c] = fmax(vals[c], 0.0);
+    double* sc = small + SL::SC;
+    sc[S_MAXRES] = mr;
+    sc[S_LAMR] = vals[rk - 1];
+    sc[S_LAMR1] = (rk < k) ? vals[rk] : __builtin_nan("");
+    sc[S_NORMW] = scale;
+    sc[S_CHOLFIX] = (double)flag[0];
+    sc[S_FILTC] = fc;
+    sc[S_FILTE] = fe;
+    sc[S_SWEEPS] = (double)sweeps;
+    bool bad = false;
+    for (int c = 0; c < k; ++c) bad |= !isfinite(vals[c]);
+    if (bad) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 1.0);
+  }
+}
+
+// Exact eigendecomposition of the n x n W (n <= KMAX) in one workgroup; the
+// top r eigenpairs become the factors (V row stride KMAX, lambda_+ at
+// lam_off), and the factor partials of the single slice are formed as in
+// k_rowwise (nslices = 1 downstream).
+__global__ __launch_bounds__(1024) void k_full_eig(const double* __restrict__ W, int64_t ld, int n,
+                                                   double* __restrict__ V, int r,
+                                                   const double* __restrict__ Vold, int r_old,
+                                                   double* __restrict__ small, int lam_off,
+                                                   int n_r1, const double* __restrict__ r1_u,
+                                                   int npad, double* __restrict__ fac_part) {
+  extern __shared__ double sm[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* A = sm;                  // n x n
+  double* U = A + n * n;           // n x n
+  double* vals = U + n * n;        // n
+  double* cs = vals + n;           // 2 (n/2 + 1) + ints
+  int* perm = reinterpret_cast<int*>(cs + 3 * (KMAX / 2 + 1));
+  int* flag = perm + KMAX;
+  for (int t = tid; t < n * n; t += nt) {
+    const int i = t / n, j = t - (t / n) * n;
+    A[t] = 0.5 * (W[(int64_t)i * ld + j] + W[(int64_t)j * ld + i]);
+  }
+  __syncthreads();
+  const int sweeps = jacobi_eig(A, n, U, n, n, cs, flag, 60);
+  sort_desc(A, n, n, vals, perm);
+  // factors
+  for (int t = tid; t < n * r; t += nt) {
+    const int i = t / r, c = t - (t / r) * r;
+    V[(int64_t)i * KMAX + c] = U[i * n + perm[c]];
+  }
+  double* theta = small + SL::THETA;
+  for (int c = tid; c < n; c += nt) {
+    theta[c] = vals[c];
+    small[SL::RES + c] = 0.0;
+  }
+  if (tid == 0) {
+    for (int c = 0; c < r; ++c) small[lam_off + c] = fmax(vals[c], 0.0);
+    double* sc = small + SL::SC;
+    sc[S_MAXRES] = 0.0;
+    sc[S_LAMR] = vals[r - 1];
+    sc[S_LAMR1] = (r < n) ? vals[r] : __builtin_nan("");
+    sc[S_NORMW] = fmax(fabs(vals[0]), fabs(vals[n - 1]));
+    sc[S_SWEEPS] = (double)sweeps;
+    bool bad = false;
+    for (int c = 0; c < n; ++c) bad |= !isfinite(vals[c]);
+    if (bad) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 2.0);
+  }
+  __syncthreads();
+  // factor partials (single slice)
+  const int n1 = r * r, n2 = r * r_old, n3 = n_r1 * r;
+  for (int t = tid; t < n1 + n2 + n3; t += nt) {
+    double acc = 0.0;
+    if (t < n1) {
+      const int a = t / r, b = t - (t / r) * r;
+      for (int i = 0; i < n; ++i) acc += U[i * n + perm[a]] * U[i * n + perm[b]];
+    } else if (t < n1 + n2) {
+      const int e = t - n1;
+      const int a = e / r_old, b = e - (e / r_old) * r_old;
+      for (int i = 0; i < n; ++i) acc += U[i * n + perm[a]] * Vold[(int64_t)i * KMAX + b];
+    } else {
+      const int e = t - n1 - n2;
+      const int q = e / r, a = e - (e / r) * r;
+      for (int i = 0; i < n; ++i) acc += r1_u[(int64_t)q * npad + i] * U[i * n + perm[a]];
+    }
+    fac_part[t] = acc;
+  }
+  for (int c = tid; c < r; c += nt) fac_part[FAC_RES + c] = 0.0;
+}
+
+// True relative Ritz residuals ||W v_c - theta_c v_c|| / max|theta| of the r kept
+// pairs from the row-wise partials; writes RES[c] and S_MAXRES (one workgroup).
+__global__ void k_reduce_res(const double* __restrict__ fac_part, int nslices, int r,
+                             double* __restrict__ small) {
+  __shared__ double red[256];
+  double worst = 0.0;
+  const double scale = fmax(small[SL::SC + S_NORMW], 1e-300);
+  const double* theta = small + SL::THETA;
+  int npos = 0;
+  while (npos < r && theta[npos] > 0.0) ++npos;
+  const int nchk = npos > 0 ? npos : (r > 0 ? 1 : 0);
+  for (int c = threadIdx.x; c < r; c += blockDim.x) {
+    double acc = 0.0;
+    for (int s = 0; s < nslices; ++s) acc += fac_part[(int64_t)s * FAC_STRIDE + FAC_RES + c];
+    const double rel = sqrt(acc) / scale;
+    small[SL::RES + c] = rel;
+    if (c < nchk) worst = fmax(worst, rel);
+  }
+  red[threadIdx.x] = worst;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) small[SL::SC + S_MAXRES] = red[0];
+}
+
+// Lower spectral bound for the filter from an unshifted block: the block has
+// converged towards the largest-magnitude eigenvalues, so -1.05 max|theta|
+// bounds the spectrum from below; the rigorous bound in S_GERSH is kept if larger.
+__global__ void k_set_lower_bound(double* __restrict__ small) {
+  if (threadIdx.x == 0) {
+    double* sc = small + SL::SC;
+    const double est = -1.05 * sc[S_NORMW];
+    sc[S_GERSH] = fmax(sc[S_GERSH], est);
+  }
+}
+
+// Reduces Gershgorin partial minima into small[S_GERSH] (one workgroup).
+__global__ void k_reduce_min(const double* __restrict__ part, int cnt, double* __restrict__ small,
+                             int slot) {
+  __shared__ double red[256];
+  double b = 1e308;
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) b = fmin(b, part[t]);
+  red[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) small[SL::SC + slot] = red[0];
+}
+
+}  // namespace proxsdp

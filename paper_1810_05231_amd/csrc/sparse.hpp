@@ -1,0 +1,283 @@
+// Sparse kernels of the PDHG step.
+//
+// gather_dual  M(X+) from the factors X+ = V diag(lambda+) V^T, then the
+//              dual step of Algorithm 1 in the Section 1.3 sign:
+//                u = y + alpha (rhs - (2 M(X+) - M(X)))
+//                y+ = u (equality rows),  y+ = min(0, u) (inequality rows)
+//              (box resolvent of Section 2.3.1 through the Moreau identity),
+//              and per-block sums for the dual residual of Section 2.2.
+// pattern      values D_e = -alpha C_e + alpha M*(y+)_e on the sparsity
+//              pattern (consumed by the dense write), the Gershgorin lower
+//              bound of D, the sparse part of ||M*(y+ - y)||_F^2, and the
+//              objective <C, X+> gathered from the factors.
+// finalize     combines the partial sums into eps_primal, eps_dual (Section
+//              2.2) and the iteration record.
+#pragma once
+
+#include "common.hpp"
+
+namespace proxsdp {
+
+__device__ inline double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+__device__ inline double block_min(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 1e308;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int w = 0; w < nw; ++w) s = fmin(s, red[w]);
+  return s;
+}
+
+// X+_{ab} from the factors (V row stride KMAX).
+__device__ inline double factor_entry(const double* V, const double* lam, int r, int a, int b) {
+  const double* va = V + (int64_t)a * KMAX;
+  const double* vb = V + (int64_t)b * KMAX;
+  double acc = 0.0;
+  for (int t = 0; t < r; ++t) acc += lam[t] * va[t] * vb[t];
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double* __restrict__ V,
+                                                     int r, const double* __restrict__ small,
+                                                     int lam_off, const double* __restrict__ fac_part,
+                                                     int nslices, int r_old,
+                                                     double* __restrict__ y,
+                                                     double* __restrict__ y_old,
+                                                     double* __restrict__ MX,
+                                                     double* __restrict__ MX_old,
+                                                     double* __restrict__ row_part) {
+  __shared__ double red[16];
+  const double* lam = small + lam_off;
+  const double alpha = small[SL::SC + S_ALPHA];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double ed2 = 0.0, cross = 0.0, dobj = 0.0, bad = 0.0;
+  if (i < dp.rows) {
+    double mx = 0.0;
+    for (int e = dp.row_ptr[i]; e < dp.row_ptr[i + 1]; ++e)
+      mx += dp.row_w[e] * factor_entry(V, lam, r, dp.row_a[e], dp.row_b[e]);
+    const int q = dp.row_r1[i];
+    if (q >= 0) {
+      // sigma_q u_q^T X+ u_q = sigma_q sum_t lam_t (u_q^T v_t)^2
+      const int off = r * r + r * r_old + q * r;
+      double acc = 0.0;
+      for (int t = 0; t < r; ++t) {
+        double uv = 0.0;
+        for (int s = 0; s < nslices; ++s) uv += fac_part[(int64_t)s * FAC_STRIDE + off + t];
+        acc += lam[t] * uv * uv;
+      }
+      mx += dp.r1_sigma[q] * acc;
+    }
+    const double mx0 = MX[i];
+    const double y0 = y[i];
+    double u = y0 + alpha * (dp.rhs[i] - (2.0 * mx - mx0));
+    if (i >= dp.m) u = fmin(u, 0.0);
+    const double dy = u - y0, dmx = mx - mx0;
+    const double rd = dy / alpha + dmx;
+    ed2 = rd * rd;
+    cross = dmx * dy;
+    dobj = dp.rhs[i] * u;
+    if (!isfinite(u) || !isfinite(mx)) bad = 1.0;
+    y_old[i] = y0;
+    y[i] = u;
+    MX_old[i] = mx0;
+    MX[i] = mx;
+  }
+  ed2 = block_sum(ed2, red);
+  cross = block_sum(cross, red);
+  dobj = block_sum(dobj, red);
+  bad = block_sum(bad, red);
+  if (threadIdx.x == 0) {
+    double* o = row_part + (int64_t)blockIdx.x * ROW_PART;
+    o[0] = ed2; o[1] = cross; o[2] = dobj; o[3] = bad;
+  }
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// One wave per row a of the symmetric pattern (rows strided over the grid);
+// lanes split the row's entries.
+__global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __restrict__ V, int r,
+                                                 const double* __restrict__ small, int lam_off,
+                                                 const double* __restrict__ y,
+                                                 const double* __restrict__ y_old,
+                                                 double* __restrict__ dval,
+                                                 double* __restrict__ pat_part, int with_obj) {
+  __shared__ double red[16];
+  const double* lam = small + lam_off;
+  const double alpha = small[SL::SC + S_ALPHA];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  double lo = 1e308, mdy2 = 0.0, obj = 0.0;
+  double crossq[MAX_R1];
+  for (int q = 0; q < MAX_R1; ++q) crossq[q] = 0.0;
+  for (int a = blockIdx.x * 4 + wave; a < dp.n; a += gridDim.x * 4) {
+    double center = 0.0, radius = 0.0;
+    for (int s = dp.sym_ptr[a] + lane; s < dp.sym_ptr[a + 1]; s += 64) {
+      const int e = dp.sym_e[s];
+      const int ea = dp.pat_a[e], eb = dp.pat_b[e];
+      double dv = -alpha * dp.pat_c[e];
+      double md = 0.0;
+      for (int t = dp.pat_rptr[e]; t < dp.pat_rptr[e + 1]; ++t) {
+        const int i = dp.pat_row[t];
+        const double v = dp.pat_val[t];
+        const double yi = y[i];
+        dv += alpha * yi * v;
+        md += (yi - y_old[i]) * v;
+      }
+      if (ea == eb)
+        center += dv;
+      else
+        radius += fabs(dv);
+      if (ea == a) {  // owner of the entry
+        dval[e] = dv;
+        const double w = (ea == eb) ? 1.0 : 2.0;
+        mdy2 += w * md * md;
+        for (int q = 0; q < dp.n_r1; ++q)
+          crossq[q] += w * md * dp.r1_u[(int64_t)q * dp.npad + ea] * dp.r1_u[(int64_t)q * dp.npad + eb];
+        if (with_obj && dp.pat_c[e] != 0.0) obj += w * dp.pat_c[e] * factor_entry(V, lam, r, ea, eb);
+      }
+    }
+    center = wave_sum(center);
+    radius = wave_sum(radius);
+    lo = fmin(lo, center - radius);
+  }
+  lo = block_min(lo, red);
+  mdy2 = block_sum(mdy2, red);
+  obj = block_sum(obj, red);
+  for (int q = 0; q < MAX_R1; ++q) crossq[q] = block_sum(crossq[q], red);
+  if (threadIdx.x == 0) {
+    double* o = pat_part + (int64_t)blockIdx.x * PAT_PART;
+    o[0] = lo; o[1] = mdy2; o[2] = obj; o[3] = 0.0;
+    for (int q = 0; q < MAX_R1; ++q) o[4 + q] = crossq[q];
+  }
+}
+
+// Runs in one workgroup (the extra block of the dense write).
+//   ||X+ - X||^2 = ||X+||^2 + ||X||^2 - 2 <X+, X> from the factor Grams,
+//   eps_p^2 = ||dX||^2 / alpha^2 + (2/alpha) <M(dX), dy> + ||M*(dy)||^2,
+//   eps_d^2 = sum (dy/alpha + M(dX))^2     (Section 2.2, sign of Section 1.3).
+__device__ void finalize_iteration(const FinArgs& f, double* small, const DevProblem& dp,
+                                   const double* y, const double* y_old, double* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double* lam = small + f.lam_new;
+  const double* lam0 = small + f.lam_old;
+  const int r = f.r, r0 = f.r_old;
+  double x2 = 0.0, x01 = 0.0;
+  for (int t = tid; t < r * r + r * r0; t += nt) {
+    double g = 0.0;
+    for (int s = 0; s < f.nslices; ++s) g += f.fac_part[(int64_t)s * FAC_STRIDE + t];
+    if (t < r * r) {
+      const int a = t / r, b = t - (t / r) * r;
+      x2 += lam[a] * lam[b] * g * g;
+    } else {
+      const int e = t - r * r;
+      const int a = e / r0, b = e - (e / r0) * r0;
+      x01 += lam[a] * lam0[b] * g * g;
+    }
+  }
+  double ed2 = 0.0, cross = 0.0, dobj = 0.0, bad = 0.0;
+  for (int b = tid; b < f.nrow_blocks; b += nt) {
+    const double* o = f.row_part + (int64_t)b * ROW_PART;
+    ed2 += o[0]; cross += o[1]; dobj += o[2]; bad += o[3];
+  }
+  double lo = 1e308, mdy2 = 0.0, obj = 0.0;
+  double cq[MAX_R1];
+  for (int q = 0; q < MAX_R1; ++q) cq[q] = 0.0;
+  for (int b = tid; b < f.npat_blocks; b += nt) {
+    const double* o = f.pat_part + (int64_t)b * PAT_PART;
+    lo = fmin(lo, o[0]); mdy2 += o[1]; obj += o[2];
+    for (int q = 0; q < MAX_R1; ++q) cq[q] += o[4 + q];
+  }
+  x2 = block_sum(x2, red);
+  x01 = block_sum(x01, red);
+  ed2 = block_sum(ed2, red);
+  cross = block_sum(cross, red);
+  dobj = block_sum(dobj, red);
+  bad = block_sum(bad, red);
+  lo = block_min(lo, red);
+  mdy2 = block_sum(mdy2, red);
+  obj = block_sum(obj, red);
+  for (int q = 0; q < MAX_R1; ++q) cq[q] = block_sum(cq[q], red);
+  // true Ritz residuals of the kept pairs (row-wise partials of the final round)
+  double worst = 0.0;
+  {
+    const double scale = fmax(small[SL::SC + S_NORMW], 1e-300);
+    const double* theta = small + SL::THETA;
+    int npos = 0;
+    while (npos < r && theta[npos] > 0.0) ++npos;
+    const int nchk = npos > 0 ? npos : (r > 0 ? 1 : 0);
+    for (int c = tid; c < nchk; c += nt) {
+      double acc = 0.0;
+      for (int s = 0; s < f.nslices; ++s) acc += f.fac_part[(int64_t)s * FAC_STRIDE + FAC_RES + c];
+      worst = fmax(worst, sqrt(acc) / scale);
+    }
+    for (int o = 32; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o));
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = worst;
+    __syncthreads();
+    const int nw = (nt + 63) >> 6;
+    for (int w = 0; w < nw; ++w) worst = fmax(worst, red[w]);
+  }
+  if (tid == 0) {
+    small[SL::SC + S_MAXRES] = worst;
+    double* sc = small + SL::SC;
+    const double alpha = sc[S_ALPHA];
+    const double x2old = sc[f.x2_old];
+    const double dx2 = fmax(x2 + x2old - 2.0 * x01, 0.0);
+    // rank-one part of M*(dy)
+    double my2 = mdy2;
+    double gamma_lo = 0.0;
+    for (int q = 0; q < dp.n_r1; ++q) {
+      const int rq = dp.r1_row[q];
+      const double dyq = y[rq] - y_old[rq];
+      my2 += 2.0 * dp.r1_sigma[q] * dyq * cq[q];
+      for (int q2 = 0; q2 < dp.n_r1; ++q2) {
+        const int rq2 = dp.r1_row[q2];
+        my2 += dp.r1_sigma[q] * dp.r1_sigma[q2] * dyq * (y[rq2] - y_old[rq2]) *
+               dp.r1_gram[q * MAX_R1 + q2];
+      }
+      gamma_lo += fmin(0.0, alpha * dp.r1_sigma[q] * y[rq] * dp.r1_norm2[q]);
+    }
+    const double ep2 = dx2 / (alpha * alpha) + 2.0 * cross / alpha + my2;
+    const double eps_p = sqrt(fmax(ep2, 0.0));
+    const double eps_d = sqrt(fmax(ed2, 0.0));
+    sc[f.x2_new] = x2;
+    sc[S_EPSP] = eps_p;
+    sc[S_EPSD] = eps_d;
+    sc[S_OBJ] = obj;
+    sc[S_DOBJ] = dobj;
+    sc[S_DX2] = dx2;
+    sc[S_GERSH] = lo + gamma_lo;
+    if (bad > 0.0) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 3.0);
+    if (!isfinite(eps_p) || !isfinite(eps_d)) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 4.0);
+    IterRecord rec;
+    rec.eps_p = eps_p;
+    rec.eps_d = eps_d;
+    rec.obj = obj;
+    rec.dual_obj = dobj;
+    rec.lambda_r = sc[S_LAMR];
+    rec.lambda_r1 = sc[S_LAMR1];
+    rec.maxres = sc[S_MAXRES];
+    rec.gersh = lo + gamma_lo;
+    f.ring[f.ring_slot] = rec;
+  }
+}
+
+}  // namespace proxsdp

@@ -1,0 +1,198 @@
+"""Python-facing wrappers of libproxsdp (argument marshalling only).
+
+PyTorch supplies device memory (the workspace tensors) and the stream; every
+step of the method runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import FP64, Info, Problem, check, default_options, lib
+
+__all__ = ["Solver", "project_psd", "problem_struct", "workspace_size"]
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a.size else None
+
+
+def problem_struct(prob):
+    """ctypes Problem view of an object with the fields of the C struct.
+
+    Returns (struct, keepalive) -- keep the second item alive while the
+    struct is in use.
+    """
+    arrs = dict(
+        c_i=np.ascontiguousarray(prob.c_i, dtype=np.int32),
+        c_j=np.ascontiguousarray(prob.c_j, dtype=np.int32),
+        c_v=np.ascontiguousarray(prob.c_v, dtype=np.float64),
+        a_row=np.ascontiguousarray(prob.a_row, dtype=np.int32),
+        a_i=np.ascontiguousarray(prob.a_i, dtype=np.int32),
+        a_j=np.ascontiguousarray(prob.a_j, dtype=np.int32),
+        a_v=np.ascontiguousarray(prob.a_v, dtype=np.float64),
+        r1_row=np.ascontiguousarray(getattr(prob, "r1_row", np.zeros(0)), dtype=np.int32),
+        r1_sigma=np.ascontiguousarray(getattr(prob, "r1_sigma", np.zeros(0)), dtype=np.float64),
+        r1_u=np.ascontiguousarray(getattr(prob, "r1_u", np.zeros(0)), dtype=np.float64).reshape(-1),
+        b=np.ascontiguousarray(prob.b, dtype=np.float64),
+        h=np.ascontiguousarray(prob.h, dtype=np.float64),
+    )
+    s = Problem()
+    s.n, s.m, s.p = int(prob.n), int(prob.m), int(prob.p)
+    s.nnz_c = arrs["c_v"].size
+    s.c_i, s.c_j, s.c_v = (_ptr(arrs["c_i"], C.c_int32), _ptr(arrs["c_j"], C.c_int32),
+                           _ptr(arrs["c_v"], C.c_double))
+    s.nnz_a = arrs["a_v"].size
+    s.a_row, s.a_i, s.a_j = (_ptr(arrs["a_row"], C.c_int32), _ptr(arrs["a_i"], C.c_int32),
+                             _ptr(arrs["a_j"], C.c_int32))
+    s.a_v = _ptr(arrs["a_v"], C.c_double)
+    s.n_r1 = arrs["r1_row"].size
+    s.r1_row = _ptr(arrs["r1_row"], C.c_int32)
+    s.r1_sigma = _ptr(arrs["r1_sigma"], C.c_double)
+    s.r1_u = _ptr(arrs["r1_u"], C.c_double)
+    s.b = _ptr(arrs["b"], C.c_double)
+    s.h = _ptr(arrs["h"], C.c_double)
+    return s, arrs
+
+
+def workspace_size(prob, **options) -> int:
+    s, keep = problem_struct(prob)
+    o = default_options(**options)
+    nb = C.c_size_t()
+    check(lib.proxsdp_workspace_size(C.byref(s), C.byref(o), C.byref(nb)),
+          "proxsdp_workspace_size")
+    return int(nb.value)
+
+
+def _device_buffer(nbytes: int, device):
+    import torch
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    addr = buf.data_ptr()
+    off = (-addr) % 256
+    return buf, addr + off
+
+
+def _stream_handle(device):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Solver:
+    """LR-PD-SDP / PD-SDP solver on one GPU.
+
+    ``prob`` is any object with the fields of ``proxsdp_problem`` as numpy
+    arrays (``instances.Problem`` is one).  Options are the fields of
+    ``proxsdp_options``.
+    """
+
+    def __init__(self, prob, device="cuda", **options):
+        import torch
+        self.device = torch.device(device)
+        self.n = int(prob.n)
+        self.rows = int(prob.m) + int(prob.p)
+        s, keep = problem_struct(prob)
+        o = default_options(**options)
+        nb = C.c_size_t()
+        check(lib.proxsdp_workspace_size(C.byref(s), C.byref(o), C.byref(nb)),
+              "proxsdp_workspace_size")
+        self.ws_bytes = int(nb.value)
+        self._buf, ptr = _device_buffer(self.ws_bytes, self.device)
+        self._h = C.c_void_p()
+        check(lib.proxsdp_create(C.byref(s), C.byref(o), C.c_void_p(ptr), self.ws_bytes,
+                                 _stream_handle(self.device), C.byref(self._h)), "proxsdp_create")
+        del keep
+
+    def step(self, n_iters: int = 1) -> dict:
+        info = Info()
+        check(lib.proxsdp_step(self._h, int(n_iters), C.byref(info)), "proxsdp_step")
+        return info.to_dict()
+
+    def solve(self) -> dict:
+        info = Info()
+        check(lib.proxsdp_solve(self._h, C.byref(info)), "proxsdp_solve")
+        return info.to_dict()
+
+    def solution(self, on_device: bool = True):
+        """(X, y): X as an n x n float64 tensor (device) or ndarray, y as ndarray."""
+        import torch
+        y = np.zeros(self.rows)
+        if on_device:
+            X = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+            check(lib.proxsdp_get_solution(self._h, C.c_void_p(X.data_ptr()),
+                                           y.ctypes.data_as(C.c_void_p), 0), "get_solution(y)")
+            check(lib.proxsdp_get_solution(self._h, C.c_void_p(X.data_ptr()), None, 1),
+                  "get_solution(X)")
+            torch.cuda.synchronize(self.device)
+            return X, y
+        X = np.zeros((self.n, self.n))
+        check(lib.proxsdp_get_solution(self._h, X.ctypes.data_as(C.c_void_p),
+                                       y.ctypes.data_as(C.c_void_p), 0), "get_solution")
+        return X, y
+
+    def factors(self):
+        r = C.c_int32()
+        check(lib.proxsdp_get_factors(self._h, None, None, C.byref(r)), "get_factors")
+        V = np.zeros((self.n, max(r.value, 1)))
+        lam = np.zeros(max(r.value, 1))
+        check(lib.proxsdp_get_factors(self._h, V.ctypes.data_as(C.POINTER(C.c_double)),
+                                      lam.ctypes.data_as(C.POINTER(C.c_double)), C.byref(r)),
+              "get_factors")
+        return V[:, :r.value], lam[:r.value]
+
+    def reset(self) -> None:
+        """Restart from X0 = 0, y0 = 0 on the data already on the device."""
+        check(lib.proxsdp_reset(self._h), "proxsdp_reset")
+
+    def debug(self) -> dict:
+        """Internal device scalars (see proxsdp_debug_scalars)."""
+        out = np.zeros(64 + 64)
+        check(lib.proxsdp_debug_scalars(self._h, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                        out.size), "debug_scalars")
+        names = {0: "alpha", 1: "lower_bound", 2: "maxres", 3: "lambda_r", 4: "lambda_r1",
+                 5: "normw", 6: "eps_p", 7: "eps_d", 8: "obj", 9: "dual_obj", 10: "dx2",
+                 13: "nonfinite", 14: "dropped", 15: "filter_c", 16: "filter_e", 17: "sweeps"}
+        d = {v: float(out[k]) for k, v in names.items()}
+        d["theta"] = out[64:].tolist()
+        return d
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.proxsdp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def project_psd(S, r: int, tol: float = 1e-12, want_P: bool = True, want_vectors: bool = False):
+    """aproj(S, r) for a device float64 tensor S (n x n, row stride S.stride(0)).
+
+    Returns (P or None, eigenvalues (r, decreasing), eigenvectors (n x r) or
+    None, number of positive kept eigenvalues).
+    """
+    import torch
+    assert S.is_cuda and S.dtype == torch.float64 and S.dim() == 2 and S.stride(1) == 1
+    n = S.shape[0]
+    re = n if (r <= 0 or r >= n) else r
+    nb = C.c_size_t()
+    check(lib.proxsdp_project_workspace_size(n, int(r), FP64, C.byref(nb)),
+          "proxsdp_project_workspace_size")
+    buf, ptr = _device_buffer(int(nb.value), S.device)
+    P = torch.empty((n, n), dtype=torch.float64, device=S.device) if want_P else None
+    evals = np.zeros(re)
+    evecs = np.zeros((n, re)) if want_vectors else None
+    rank = C.c_int32()
+    check(lib.proxsdp_project_psd(
+        C.c_void_p(S.data_ptr()), n, S.stride(0), int(r), FP64, float(tol),
+        C.c_void_p(P.data_ptr()) if P is not None else None, n,
+        evals.ctypes.data_as(C.POINTER(C.c_double)),
+        evecs.ctypes.data_as(C.POINTER(C.c_double)) if evecs is not None else None,
+        C.byref(rank), C.c_void_p(ptr), int(nb.value), _stream_handle(S.device)),
+        "proxsdp_project_psd")
+    del buf
+    return P, evals, evecs, int(rank.value)

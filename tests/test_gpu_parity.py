@@ -1,0 +1,161 @@
+"""GPU parity tests: the HIP path (through the C interface) against the FP64
+oracle on the same seeded inputs.
+
+Tolerances:
+* projection entry point, FP64: ||P_gpu - P_oracle||_max <= 1e-9 ||S||_2 for
+  the exact Jacobi path and for the partial eigensolve run to a relative
+  Ritz residual of 1e-12 (spectra with a gap of at least 10% of ||S||).
+* iterates after K PDHG steps with converged eigensolves: max abs
+  difference <= 1e-7 (relative to max |X|).
+* solves to rho <= 1e-4: objective within 1e-5 relative of the oracle's
+  objective at the same tolerance, and the oracle's certificate of the GPU
+  answer (one exact PDHG step from it) below 2e-4.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import instances as I
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_device_properties(torch_cuda):
+    p = torch_cuda.cuda.get_device_properties(0)
+    _say("device", p.name, "CUs", p.multi_processor_count, "mem GB", p.total_memory / 2**30)
+    assert p.multi_processor_count >= 1
+
+
+# ----------------------------------------------------------- projection
+@pytest.mark.parametrize("n,r,seed", [(50, 0, 0), (50, 5, 1), (17, 3, 2), (64, 0, 3), (1, 0, 4)])
+def test_project_full_path(torch_cuda, n, r, seed):
+    from paper_1810_05231_amd import project_psd
+    _say("project_full", n, r, seed)
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    S = 0.5 * (A + A.T)
+    St = torch_cuda.tensor(S, device="cuda")
+    P, ev, vec, rank = project_psd(St, r, want_vectors=True)
+    want = O.proj_psd(S) if (r == 0 or r >= n) else O.aproj_psd(S, r)
+    scale = max(1.0, np.abs(np.linalg.eigvalsh(S)).max())
+    assert np.abs(P.cpu().numpy() - want).max() <= 1e-9 * scale
+    lam = np.sort(np.linalg.eigvalsh(S))[::-1]
+    re = n if (r == 0 or r >= n) else r
+    assert np.allclose(ev, lam[:re], atol=1e-10 * scale)
+    assert rank == int(np.sum(lam[:re] > 0))
+
+
+@pytest.mark.parametrize("n,r,rpos,seed", [(257, 4, 4, 0), (300, 1, 3, 1), (1000, 8, 8, 2),
+                                           (1000, 16, 5, 3), (513, 8, 12, 4)])
+def test_project_partial_path(torch_cuda, n, r, rpos, seed):
+    from paper_1810_05231_amd import project_psd
+    _say("project_partial", n, r, rpos, seed)
+    lam = I.lowrank_plus_negative_spectrum(n, rpos, seed)
+    S = I.random_symmetric(n, lam, seed)
+    St = torch_cuda.tensor(S, device="cuda")
+    P, ev, vec, rank = project_psd(St, r, tol=1e-12, want_vectors=True)
+    want = O.aproj_psd(S, r)
+    scale = np.abs(lam).max()
+    err = np.abs(P.cpu().numpy() - want).max()
+    _say("  max err", err, "scale", scale)
+    assert err <= 1e-9 * scale
+    srt = np.sort(lam)[::-1]
+    npos = min(r, rpos)
+    # the kept positive pairs are converged; Ritz values below zero inside a
+    # gapless cluster do not enter aproj and are not required to converge
+    nchk = npos
+    assert np.allclose(ev[:nchk], srt[:nchk], atol=1e-9 * scale)
+    assert rank == npos
+    assert np.allclose(vec.T @ vec, np.eye(r), atol=1e-10)
+    assert np.abs(S @ vec[:, :nchk] - vec[:, :nchk] * ev[:nchk]).max() <= 1e-9 * scale
+
+
+def test_project_ragged_leading_dimension(torch_cuda):
+    from paper_1810_05231_amd import project_psd
+    n = 131
+    lam = I.lowrank_plus_negative_spectrum(n, 3, 9)
+    S = I.random_symmetric(n, lam, 9)
+    big = torch_cuda.zeros((n, n + 7), dtype=torch_cuda.float64, device="cuda")
+    big[:, :n] = torch_cuda.tensor(S, device="cuda")
+    P, ev, _, _ = project_psd(big[:, :n], 3, tol=1e-12)
+    assert np.abs(P.cpu().numpy() - O.aproj_psd(S, 3)).max() <= 1e-9 * np.abs(lam).max()
+
+
+# -------------------------------------------------------------- iterates
+def _oracle_steps(prob, K, r, alpha):
+    ops = O.Operators(prob)
+    C = ops.C()
+    X = np.zeros((prob.n, prob.n))
+    y = np.zeros(prob.m + prob.p)
+    for _ in range(K):
+        out = O.pdhg_step(ops, C, X, y, r, alpha)
+        X, y = out.X, out.y
+    return X, y / ops.scale, out
+
+
+@pytest.mark.parametrize("kind,n,r,K", [("maxcut", 50, 4, 25), ("maxcut", 50, 50, 25),
+                                        ("equip", 40, 2, 25), ("maxcut", 200, 4, 20),
+                                        ("equip", 180, 3, 20)])
+def test_iterates_match_oracle(torch_cuda, kind, n, r, K):
+    from paper_1810_05231_amd import Solver
+    _say("iterates", kind, n, r, K)
+    prob = I.maxcut(n, 0.1, 7) if kind == "maxcut" else I.equipartition(n, 0.1, 7)
+    alpha = 0.95 / O.Operators(prob).norm()
+    s = Solver(prob, r0=r, alpha=alpha, check_every=5, window=1000, eig_strict=1,
+               eig_tol=1e-13, full_eig=1 if r == n else 0, max_iters=K)
+    info = s.step(K)
+    _say("  info", info["status_name"], info["iters"], "debug", {k: v for k, v in s.debug().items()
+                                                               if k != "theta"})
+    Xg, yg = s.solution(on_device=False)
+    Xo, yo, out = _oracle_steps(prob, K, r, alpha)
+    scale = max(1.0, np.abs(Xo).max())
+    _say("  dX", np.abs(Xg - Xo).max() / scale, "dy", np.abs(yg - yo).max())
+    assert info["iters"] == K
+    assert np.abs(Xg - Xo).max() <= 1e-7 * scale
+    assert np.abs(yg - yo).max() <= 1e-7 * max(1.0, np.abs(yo).max())
+    # residuals of the last step
+    assert info["eps_p"] == pytest.approx(out.eps_p, rel=1e-5, abs=1e-9)
+    assert info["eps_d"] == pytest.approx(out.eps_d, rel=1e-5, abs=1e-9)
+    s.close()
+
+
+# ---------------------------------------------------------------- solves
+@pytest.mark.parametrize("kind,n,seed,full", [("maxcut", 50, 0, False), ("maxcut", 50, 1, True),
+                                              ("maxcut", 50, 2, False), ("equip", 50, 0, False),
+                                              ("maxcut", 150, 3, False), ("equip", 120, 4, False)])
+def test_solve_matches_oracle(torch_cuda, kind, n, seed, full):
+    from paper_1810_05231_amd import Solver
+    _say("solve", kind, n, seed, full)
+    p_edge = 0.1 if n <= 50 else 0.05
+    prob = I.maxcut(n, p_edge, seed) if kind == "maxcut" else I.equipartition(n, p_edge, seed)
+    s = Solver(prob, tol=1e-4, full_eig=int(full))
+    info = s.solve()
+    _say("  gpu", info["status_name"], info["iters"], info["r"], info["obj"], info["time_s"])
+    if info["status_name"] != "converged":
+        _say("  debug", s.debug())
+    assert info["status_name"] == "converged"
+    X, y = s.solution(on_device=False)
+    ref = O.solve(prob, tol=1e-4, full_eig=full)
+    _say("  oracle", ref.iters, ref.r, ref.obj)
+    cert = O.certificate(prob, X, y)
+    _say("  cert", cert.rho_p, cert.rho_d, cert.rel_gap)
+    assert info["obj"] == pytest.approx(ref.obj, rel=1e-5)
+    assert max(cert.rho_p, cert.rho_d) <= 2e-4
+    assert cert.lambda_min_X >= -1e-9 * max(1.0, np.abs(X).max())
+    s.close()
