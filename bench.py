@@ -95,7 +95,7 @@ def main():
         profs.append(prof)
         log(f"step {k}: {info['status_name']} iters={info['iters']} r={info['r']} "
             f"passes={info['passes']} wall={dt:.3f}s obj={info['obj']:.8f} "
-            f"rho=({info['rho_p']:.2e},{info['rho_d']:.2e})")
+            f"rho=({info['rho_p']:.2e},{info['rho_d']:.2e}) rank path {s.rank_path()}")
     ms_per_step = 1000.0 * sum(times) / len(times)
     last = infos[-1]
     # roofline of the dominant kernel: the dense pass Z = W B (FP64 MFMA), bytes = 8 n^2 per launch
@@ -145,7 +145,7 @@ def main():
             "n": n, "edges": int(prob.meta["edges"]), "tol": args.tol,
             "iters": last["iters"], "final_rank": last["r"], "passes": last["passes"],
             "obj": last["obj"], "rho_p": last["rho_p"], "rho_d": last["rho_d"],
-            "setup_s": round(setup_s, 3),
+            "setup_s": round(setup_s, 3), "rank_path": s.rank_path(),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -186,6 +186,14 @@ int proxsdp_profile_enable(proxsdp_handle *h, int32_t enable);
 int proxsdp_profile_read(proxsdp_handle *h, double *pass_ms, int32_t *pass_count,
                          double *write_ms, int32_t *write_count);
 
+/* Rank path of Algorithm 2 since create/reset: for each change of the target
+ * rank, the iteration after which it happened, the new rank and the reason
+ * (1 = residual converged but the rank test failed, 2 = the windowed residual
+ * test found no decrease).  Writes up to `cap` entries; *count gets the total.
+ * Host pointers; any may be NULL. */
+int proxsdp_rank_path(proxsdp_handle *h, int32_t *iters, int32_t *ranks, int32_t *reasons,
+                      int32_t cap, int32_t *count);
+
 /* Diagnostics: copies min(count, 64) internal device scalars to host `out`
  * (0 step size, 1 lower spectral bound used by the filter, 2 largest relative
  * Ritz residual of the kept pairs, 3 lambda_r, 4 lambda_{r+1}, 5 max |theta|,

@@ -72,6 +72,34 @@ __global__ __launch_bounds__(256) void k_block_partial_f64(
   }
 }
 
+// Gram partials of one SLICE-row block on MFMA f64 16x16x4:
+//   out[0] = X^T X, out[1] = X^T Y, out[2] = Y^T Y  (k x k each, row-major),
+// X, Y: SLICE x k in LDS (row stride k).  Output blocks of 16 x 16 are dealt
+// to the waves; operands  A[m][kk] = P[i0 + kk][a0 + m], B[kk][n] = Q[i0 + kk][b0 + n].
+__device__ inline void gram_blocks_mfma(const double* X, const double* Y, int k, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int kb = k / 16;
+  const int nblk = 3 * kb * kb;
+  const int m = lane & 15, kq = lane >> 4;
+  for (int blk = wave; blk < nblk; blk += nw) {
+    const int which = blk / (kb * kb);
+    const int rem = blk - which * kb * kb;
+    const int a0 = (rem / kb) * 16, b0 = (rem - (rem / kb) * kb) * 16;
+    const double* Pm = (which == 2) ? Y : X;
+    const double* Qm = (which == 0) ? X : Y;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int i0 = 0; i0 < SLICE; i0 += 4) {
+      const double a = Pm[(i0 + kq) * k + a0 + m];
+      const double b = Qm[(i0 + kq) * k + b0 + m];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    double* o = out + (int64_t)which * k * k;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) o[(a0 + kq + 4 * v) * k + b0 + m] = acc[v];
+  }
+}
+
 // Sums partials into Z, optional Chebyshev step, Gram partials per slice.
 //   cheb 0: Z = W B;   1: Z = (W B - c B) / e;   2: Z = 2 (W B - c B) / e - Bprev
 __global__ __launch_bounds__(256) void k_reduce_gram(const double* __restrict__ part, int nchunks,
@@ -102,27 +130,30 @@ __global__ __launch_bounds__(256) void k_reduce_gram(const double* __restrict__ 
   }
   if (!grams) return;
   __syncthreads();
-  const int kk = k * k;
-  double* out = gram_part + (int64_t)s * 3 * kk;
-  for (int t = threadIdx.x; t < 3 * kk; t += blockDim.x) {
-    const int which = t / kk;
-    const int e = t - which * kk;
-    const int a = e / k, b = e - a * k;
-    const double* X = (which == 2) ? sZ : sB;
-    const double* Y = (which == 0) ? sB : sZ;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int i = 0; i < SLICE; ++i) acc += X[i * k + a] * Y[i * k + b];
-    out[t] = acc;
-  }
+  gram_blocks_mfma(sB, sZ, k, gram_part + (int64_t)s * 3 * k * k);
 }
 
-// Per slice of SLICE rows:
-//   Vs = B S[:, :r], ZS = Z S[:, :r]  (Ritz vectors and W times them)
-//   residual partials ||ZS_c - theta_c Vs_c||^2 over the slice -> fac_part[FAC_RES + c]
-//   V = Vs (row stride KMAX)                                  if V
-//   Bn = Z MZ + B MB (row stride k)                           if Bn
-//   factor partials [V^T V | V^T Vold | u_q^T V]              if V
+// Per slice of SLICE rows (all products on MFMA f64 16x16x4):
+//   Vs = B S[:, :rp], ZS = Z S[:, :rp]   (Ritz vectors and W times them; rp = r rounded to 16)
+//   residual partials ||ZS_c - theta_c Vs_c||^2 over the slice -> fac_part[FAC_RES + c], c < r
+//   V = Vs[:, :r] (row stride KMAX)                              if V
+//   Bn = Z MZ + B MB (row stride k)                              if Bn
+//   factor partials [V^T V | V^T Vold | u_q^T V]                 if V
+// LDS: B, Z with row stride k + 1 and Vs, ZS with row stride rp + 1 (odd
+// strides keep the 16 lanes of an MFMA operand column on distinct banks).
+__device__ inline d4 mfma_rows_times_small(const double* Xl, int ldx, int row0,
+                                           const double* Sg, int ldS, int col0, int k, d4 acc) {
+  // acc[m][n] += sum_q Xl[row0 + m][q] * Sg[q][col0 + n]
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, kq = lane >> 4;
+  for (int q0 = 0; q0 < k; q0 += 4) {
+    const double a = Xl[(row0 + m) * ldx + q0 + kq];
+    const double b = Sg[(q0 + kq) * ldS + col0 + m];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
 __global__ __launch_bounds__(256) void k_rowwise(const double* __restrict__ B,
                                                  const double* __restrict__ Z,
                                                  const double* __restrict__ small, int k,
@@ -132,40 +163,53 @@ __global__ __launch_bounds__(256) void k_rowwise(const double* __restrict__ B,
                                                  const double* __restrict__ r1_u, int npad,
                                                  double* __restrict__ fac_part) {
   extern __shared__ double sm[];
-  double* sB = sm;
-  double* sZ = sB + SLICE * k;
-  double* sV = sZ + SLICE * k;
-  double* sZS = sV + SLICE * r;
+  const int rp = (r + 15) & ~15;
+  const int ldk = k + 1, ldr = rp + 1;
+  double* sB = sm;                   // SLICE x ldk
+  double* sZ = sB + SLICE * ldk;     // SLICE x ldk
+  double* sV = sZ + SLICE * ldk;     // SLICE x ldr
+  double* sZS = sV + SLICE * ldr;    // SLICE x ldr
   const int s = blockIdx.x;
   const int i0 = s * SLICE;
   const int64_t base = (int64_t)i0 * k;
   for (int t = threadIdx.x; t < SLICE * k; t += blockDim.x) {
-    sB[t] = B[base + t];
-    sZ[t] = Z[base + t];
+    const int i = t / k, c = t - (t / k) * k;
+    sB[i * ldk + c] = B[base + t];
+    sZ[i * ldk + c] = Z[base + t];
   }
   __syncthreads();
   const double* S = small + SL::S;
   const double* MZ = small + SL::MZ;
   const double* MB = small + SL::MB;
-  for (int t = threadIdx.x; t < SLICE * r; t += blockDim.x) {
-    const int i = t / r, c = t - (t / r) * r;
-    double acc = 0.0, accz = 0.0;
-    for (int q = 0; q < k; ++q) {
-      const double sq = S[q * KMAX + c];
-      acc += sB[i * k + q] * sq;
-      accz += sZ[i * k + q] * sq;
-    }
-    sV[t] = acc;
-    sZS[t] = accz;
-    if (V) V[(int64_t)(i0 + i) * KMAX + c] = acc;
-  }
-  if (Bn) {
-    for (int t = threadIdx.x; t < SLICE * k; t += blockDim.x) {
-      const int i = t / k, c = t - (t / k) * k;
-      double acc = 0.0;
-      for (int q = 0; q < k; ++q)
-        acc += sZ[i * k + q] * MZ[q * KMAX + c] + sB[i * k + q] * MB[q * KMAX + c];
-      Bn[base + t] = acc;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
+  const int rb = rp / 16, kb = k / 16;
+  // jobs: [Vs blocks: 4 x rb] [ZS blocks: 4 x rb] [Bn blocks: 4 x kb]
+  const int nV = 4 * rb, nBn = Bn ? 4 * kb : 0;
+  for (int job = wave; job < 2 * nV + nBn; job += nw) {
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    if (job < 2 * nV) {
+      const bool isZ = job >= nV;
+      const int jb = isZ ? job - nV : job;
+      const int row0 = (jb / rb) * 16, col0 = (jb - (jb / rb) * rb) * 16;
+      acc = mfma_rows_times_small(isZ ? sZ : sB, ldk, row0, S, KMAX, col0, k, acc);
+      double* dst = isZ ? sZS : sV;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + kq + 4 * v, col = col0 + m;
+        dst[row * ldr + col] = acc[v];
+        if (!isZ && V && col < r) V[(int64_t)(i0 + row) * KMAX + col] = acc[v];
+      }
+    } else {
+      const int jb = job - 2 * nV;
+      const int row0 = (jb / kb) * 16, col0 = (jb - (jb / kb) * kb) * 16;
+      acc = mfma_rows_times_small(sZ, ldk, row0, MZ, KMAX, col0, k, acc);
+      acc = mfma_rows_times_small(sB, ldk, row0, MB, KMAX, col0, k, acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + kq + 4 * v, col = col0 + m;
+        Bn[base + (int64_t)row * k + col] = acc[v];
+      }
     }
   }
   __syncthreads();
@@ -175,28 +219,44 @@ __global__ __launch_bounds__(256) void k_rowwise(const double* __restrict__ B,
     const double th = theta[c];
     double acc = 0.0;
     for (int i = 0; i < SLICE; ++i) {
-      const double d = sZS[i * r + c] - th * sV[i * r + c];
+      const double d = sZS[i * ldr + c] - th * sV[i * ldr + c];
       acc += d * d;
     }
     out[FAC_RES + c] = acc;
   }
   if (!V) return;
-  const int n1 = r * r, n2 = r * r_old, n3 = n_r1 * r;
-  for (int t = threadIdx.x; t < n1 + n2 + n3; t += blockDim.x) {
-    double acc = 0.0;
-    if (t < n1) {
-      const int a = t / r, b = t - (t / r) * r;
-      for (int i = 0; i < SLICE; ++i) acc += sV[i * r + a] * sV[i * r + b];
-    } else if (t < n1 + n2) {
-      const int e = t - n1;
-      const int a = e / r_old, b = e - (e / r_old) * r_old;
-      for (int i = 0; i < SLICE; ++i) acc += sV[i * r + a] * Vold[(int64_t)(i0 + i) * KMAX + b];
-    } else {
-      const int e = t - n1 - n2;
-      const int q = e / r, a = e - (e / r) * r;
-      for (int i = 0; i < SLICE; ++i) acc += r1_u[(int64_t)q * npad + i0 + i] * sV[i * r + a];
+  // factor Grams on MFMA: V^T V (rb x rb blocks) and V^T Vold (rb x rob blocks)
+  const int rop = (r_old + 15) & ~15;
+  const int rob = rop / 16;
+  const int n1 = r * r;
+  for (int job = wave; job < rb * rb + rb * rob; job += nw) {
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    const bool old = job >= rb * rb;
+    const int jb = old ? job - rb * rb : job;
+    const int nbk = old ? rob : rb;
+    const int a0 = (jb / nbk) * 16, b0 = (jb - (jb / nbk) * nbk) * 16;
+    for (int q0 = 0; q0 < SLICE; q0 += 4) {
+      const double a = sV[(q0 + kq) * ldr + a0 + m];
+      const double b = old ? ((b0 + m < r_old) ? Vold[(int64_t)(i0 + q0 + kq) * KMAX + b0 + m] : 0.0)
+                           : sV[(q0 + kq) * ldr + b0 + m];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
-    out[t] = acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ra = a0 + kq + 4 * v, cb = b0 + m;
+      if (!old) {
+        if (ra < r && cb < r) out[ra * r + cb] = acc[v];
+      } else {
+        if (ra < r && cb < r_old) out[n1 + ra * r_old + cb] = acc[v];
+      }
+    }
+  }
+  const int n2 = r * r_old;
+  for (int t = threadIdx.x; t < n_r1 * r; t += blockDim.x) {
+    const int q = t / r, a = t - (t / r) * r;
+    double acc = 0.0;
+    for (int i = 0; i < SLICE; ++i) acc += r1_u[(int64_t)q * npad + i0 + i] * sV[i * ldr + a];
+    out[n1 + n2 + t] = acc;
   }
 }
 
@@ -274,34 +334,53 @@ __global__ __launch_bounds__(256) void k_write_w(double* __restrict__ W, int64_t
   const int a0 = I * TILE, b0 = J * TILE;
   const int nq = rank1 ? dp.n_r1 : 0;
   const int rr = r + nq;
-  double* sT = sm;                          // 64 x 65
-  double* sVa = sT + TILE * (TILE + 1);     // 64 x rr
-  double* sVb = sVa + TILE * (rr > 0 ? rr : 1);
+  const int rrp = (rr + 3) & ~3;          // contraction length, multiple of 4
+  const int lds = rrp + 1;                // odd stride against bank conflicts
+  double* sT = sm;                        // 64 x 65
+  double* sVa = sT + TILE * (TILE + 1);   // 64 x lds:  V rows of the tile's row block
+  double* sVb = sVa + TILE * lds;         // 64 x lds:  lam-scaled V rows of the column block
   const double* lam = small + lam_off;
   const double alpha = small[SL::SC + S_ALPHA];
-  for (int t = threadIdx.x; t < TILE * rr; t += blockDim.x) {
-    const int i = t / rr, q = t - (t / rr) * rr;
+  for (int t = threadIdx.x; t < TILE * rrp; t += blockDim.x) {
+    const int i = t / rrp, q = t - (t / rrp) * rrp;
     double va = 0.0, vb = 0.0;
     if (q < r) {
       if (a0 + i < n) va = V[(int64_t)(a0 + i) * ldv + q];
       if (b0 + i < n) vb = V[(int64_t)(b0 + i) * ldv + q] * lam[q];
-    } else {
+    } else if (q < rr) {
       const int u = q - r;
       const double gamma = alpha * dp.r1_sigma[u] * y[dp.r1_row[u]];
       va = dp.r1_u[(int64_t)u * dp.npad + a0 + i];
       vb = dp.r1_u[(int64_t)u * dp.npad + b0 + i] * gamma;
     }
-    sVa[t] = va;
-    sVb[t] = vb;
+    sVa[i * lds + q] = va;
+    sVb[i * lds + q] = vb;
   }
   __syncthreads();
-  const int c = threadIdx.x & 63;
+  // low-rank part on MFMA f64 16x16x4: wave w owns rows [16w, 16w + 16) of the tile,
+  //   A[m][kk] = Va[16w + m][t0 + kk],  B[kk][n] = lam Vb[16 nb + n][t0 + kk]
+  const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  for (int q = 0; q < TILE / 4; ++q) {
-    const int a = w + 4 * q;
-    double acc = 0.0;
-    for (int t = 0; t < rr; ++t) acc += sVa[a * rr + t] * sVb[c * rr + t];
-    sT[a * (TILE + 1) + c] = acc;
+  {
+    d4 acc[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = d4{0.0, 0.0, 0.0, 0.0};
+    const int m = lane & 15, kq = lane >> 4;
+    for (int t0 = 0; t0 < rrp; t0 += 4) {
+      const double a = sVa[(16 * w + m) * lds + t0 + kq];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const double b = sVb[(16 * nb + m) * lds + t0 + kq];
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[nb], 0, 0, 0);
+      }
+    }
+    // result lane l, register v: row l/16 + 4 v, column l % 16
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        sT[(16 * w + kq + 4 * v) * (TILE + 1) + 16 * nb + m] = acc[nb][v];
+    }
   }
   if (sparse) {
     __syncthreads();
@@ -312,13 +391,11 @@ __global__ __launch_bounds__(256) void k_write_w(double* __restrict__ W, int64_t
     }
   }
   __syncthreads();
+  const int c = lane;
   for (int q = 0; q < TILE / 4; ++q) {
     const int a = w + 4 * q;
     const int ga = a0 + a, gb = b0 + c;
     if (ga < n && gb < n) W[(int64_t)ga * ld + gb] = sT[a * (TILE + 1) + c];
-    else if (ga < n + TILE && gb < ld) {
-      // padding inside the caller-visible region stays zero for internal buffers
-    }
   }
 }
 

@@ -458,6 +458,7 @@ struct proxsdp_handle {
   int m_rounds = 2;
   int status = PROXSDP_STATUS_RUNNING;
   std::vector<double> hist;
+  std::vector<int> path_it, path_r, path_why;
   double eps_lambda = 0;
   double time_s = 0;
   proxsdp_info last{};
@@ -586,15 +587,26 @@ static void zero(double* x, size_t count, hipStream_t st) {
   hipLaunchKernelGGL(k_zero, dim3((unsigned)((c + 255) / 256)), dim3(256), 0, st, x, c);
 }
 
+// Raises the dynamic LDS limit of the kernels that need more than 64 KB to
+// 160 KB minus the kernel's static LDS.
+static int set_lds_one(const void* fn) {
+  hipFuncAttributes at{};
+  HIP_OK(hipFuncGetAttributes(&at, fn));
+  const int total = 160 * 1024;
+  const int dyn = total - (int)at.sharedSizeBytes;
+  HIP_OK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, dyn));
+  return PROXSDP_OK;
+}
+
 static int set_lds_limits() {
   static bool done = false;
   if (done) return PROXSDP_OK;
-  const int big = 160 * 1024;
-  HIP_OK(hipFuncSetAttribute((const void*)k_reduce_gram, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIP_OK(hipFuncSetAttribute((const void*)k_small_rr, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIP_OK(hipFuncSetAttribute((const void*)k_rowwise, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIP_OK(hipFuncSetAttribute((const void*)k_full_eig, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIP_OK(hipFuncSetAttribute((const void*)k_write_w, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  int rc;
+  if ((rc = set_lds_one((const void*)k_reduce_gram))) return rc;
+  if ((rc = set_lds_one((const void*)k_small_rr))) return rc;
+  if ((rc = set_lds_one((const void*)k_rowwise))) return rc;
+  if ((rc = set_lds_one((const void*)k_full_eig))) return rc;
+  if ((rc = set_lds_one((const void*)k_write_w))) return rc;
   done = true;
   return PROXSDP_OK;
 }
@@ -630,15 +642,18 @@ static void launch_reduce(const double* part, int nchunks, double* Z, const doub
 
 static void launch_rr(const double* gram_part, int nsl, double* small, int k, int r, int lam_off,
                       int filter, hipStream_t st) {
-  const size_t lds = (3 * (size_t)k * k + 2 * KMAX + 3 * (KMAX / 2 + 1)) * sizeof(double) +
+  const int kk = k * k;
+  hipLaunchKernelGGL(k_sum_grams, dim3((3 * kk + 255) / 256), dim3(256), 0, st, gram_part, nsl, k,
+                     small);
+  const size_t lds = (3 * (size_t)k * k + 3 * KMAX + 3 * (KMAX / 2 + 1)) * sizeof(double) +
                      (KMAX + 4) * sizeof(int);
-  hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(512), lds, st, gram_part, nsl, small, k, r, lam_off,
-                     filter);
+  hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(256), lds, st, small, k, r, lam_off, filter);
 }
 
 static void launch_rowwise(proxsdp_handle* H, const double* B, double* V, int r, const double* Vold,
                            int r_old, double* Bn, hipStream_t st) {
-  const size_t lds = (2 * (size_t)SLICE * H->k + 2 * (size_t)SLICE * std::max(r, 1)) * sizeof(double);
+  const int rp = (r + 15) & ~15;
+  const size_t lds = (2 * (size_t)SLICE * (H->k + 1) + 2 * (size_t)SLICE * (rp + 1)) * sizeof(double);
   hipLaunchKernelGGL(k_rowwise, dim3(H->nsl), dim3(256), lds, st, B, H->Z, H->small, H->k, V, r,
                      Vold, r_old, Bn, H->dp.n_r1, H->dp.r1_u, H->npad, H->fac_part);
 }
@@ -656,7 +671,8 @@ static void launch_write(proxsdp_handle* H, double* Wout, int64_t ld, const doub
                          int lam_off, bool sparse, bool rank1, const FinArgs* fin) {
   const int ts = H->npad / TILE;
   const int rr = r + (rank1 ? H->dp.n_r1 : 0);
-  const size_t lds = ((size_t)TILE * (TILE + 1) + 2 * (size_t)TILE * std::max(rr, 1)) * sizeof(double);
+  const int rrp = (rr + 3) & ~3;
+  const size_t lds = ((size_t)TILE * (TILE + 1) + 2 * (size_t)TILE * (rrp + 1)) * sizeof(double);
   FinArgs f{};
   if (fin) f = *fin;
   hipLaunchKernelGGL(k_write_w, dim3(ts * ts + (fin ? 1 : 0)), dim3(256), lds, H->st, Wout, ld,
@@ -750,10 +766,13 @@ static void iterate_once(proxsdp_handle* H) {
   H->iters += 1;
 }
 
-static void set_rank(proxsdp_handle* H, int r_new) {
+static void set_rank(proxsdp_handle* H, int r_new, int why) {
   if (r_new == H->r) return;
   H->r = r_new;
   H->rank_updates += 1;
+  H->path_it.push_back(H->iters);
+  H->path_r.push_back(r_new);
+  H->path_why.push_back(why);
   if (H->full) return;
   const int k_new = H->opt.block ? H->opt.block : k_for_r(r_new);
   if (k_new != H->k) {
@@ -828,14 +847,14 @@ static int control(proxsdp_handle* H) {
     } else if (H->r >= H->r_cap) {
       H->hist.push_back(comb);
     } else {
-      set_rank(H, std::min(2 * H->r, H->r_cap));
+      set_rank(H, std::min(2 * H->r, H->r_cap), 1);
       H->hist.clear();
     }
   } else {
     H->hist.push_back(comb);
     if (H->r < H->r_cap && (int)H->hist.size() > L &&
         H->hist.back() >= H->hist[H->hist.size() - 1 - L]) {
-      set_rank(H, std::min(2 * H->r, H->r_cap));
+      set_rank(H, std::min(2 * H->r, H->r_cap), 2);
       H->hist.clear();
     }
   }
@@ -898,6 +917,9 @@ static int init_state(proxsdp_handle* H) {
   H->m_rounds = 2;
   H->status = PROXSDP_STATUS_RUNNING;
   H->hist.clear();
+  H->path_it.clear();
+  H->path_r.clear();
+  H->path_why.clear();
   H->time_s = 0;
   H->last = proxsdp_info{};
   H->bcur = 0;
@@ -1297,6 +1319,20 @@ int proxsdp_profile_read(proxsdp_handle* H, double* pass_ms, int32_t* pass_count
   if (write_ms) *write_ms = tw;
   if (write_count) *write_count = H->n_write;
   H->prof = false;
+  return PROXSDP_OK;
+}
+
+int proxsdp_rank_path(proxsdp_handle* H, int32_t* iters, int32_t* ranks, int32_t* reasons,
+                      int32_t cap, int32_t* count) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  const int n = (int)H->path_it.size();
+  if (count) *count = n;
+  for (int i = 0; i < n && i < cap; ++i) {
+    if (iters) iters[i] = H->path_it[i];
+    if (ranks) ranks[i] = H->path_r[i];
+    if (reasons) reasons[i] = H->path_why[i];
+  }
   return PROXSDP_OK;
 }
 

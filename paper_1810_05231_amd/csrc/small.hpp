@@ -21,7 +21,11 @@ __device__ inline int rr_player(int pos, int rnd, int kk) {
 
 // Symmetric eigendecomposition of A (k x k, LDS, stride lda) in place: on exit
 // the diagonal holds the eigenvalues and U (LDS, stride ldu) the eigenvectors
-// (columns).  `rot` is LDS scratch of 3 * (k/2 + 1) doubles + ints.
+// (columns).  Each round applies the k/2 disjoint rotations of the
+// round-robin ordering; the two-sided update is done per 2 x 2 block
+// (J_i^T A_ij J_j), so a round needs two barriers.  Sweeps stop when the
+// off-diagonal norm is below 1e-15 of the diagonal norm.
+// `cs` is LDS scratch of 3 (KMAX/2 + 1) doubles; `red` of 2 doubles.
 // Returns the number of sweeps.
 __device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double* cs, int* flag,
                           int max_sweeps) {
@@ -37,10 +41,27 @@ __device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double*
   int* pp = reinterpret_cast<int*>(cs + 2 * np);
   int* qq = pp + np;
   int sweeps = 0;
-  __syncthreads();
+  __shared__ double offd[2];
   for (int sw = 0; sw < max_sweeps; ++sw) {
-    if (tid == 0) *flag = 0;
+    // convergence test on the off-diagonal mass
+    if (tid == 0) { offd[0] = 0.0; offd[1] = 0.0; *flag = 0; }
     __syncthreads();
+    double off = 0.0, dg = 0.0;
+    for (int t = tid; t < k * k; t += nt) {
+      const int i = t / k, j = t - (t / k) * k;
+      const double v = A[i * lda + j];
+      if (i == j) dg += v * v; else off += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      dg += __shfl_xor(dg, o);
+    }
+    if ((tid & 63) == 0) {
+      atomicAdd(&offd[0], off);
+      atomicAdd(&offd[1], dg);
+    }
+    __syncthreads();
+    if (!(offd[0] > 1e-30 * offd[1]) || !(offd[0] > 1e-300)) break;
     for (int rnd = 0; rnd < kk - 1; ++rnd) {
       for (int i = tid; i < np; i += nt) {
         int p = rr_player(i, rnd, kk), q = rr_player(kk - 1 - i, rnd, kk);
@@ -54,45 +75,43 @@ __device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double*
             const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
             s = t * c;
-            *flag = 1;
           }
         }
         cc[i] = c; ss[i] = s; pp[i] = p; qq[i] = (q < k) ? q : -1;
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int t = tid; t < np * k; t += nt) {
-        const int i = t / k, j = t - (t / k) * k;
-        const int q = qq[i];
-        if (q < 0 || ss[i] == 0.0) continue;
-        const int p = pp[i];
-        const double c = cc[i], s = ss[i];
-        const double ap = A[p * lda + j], aq = A[q * lda + j];
-        A[p * lda + j] = c * ap - s * aq;
-        A[q * lda + j] = s * ap + c * aq;
+      // A <- J^T A J blockwise; U <- U J
+      for (int t = tid; t < np * np; t += nt) {
+        const int bi = t / np, bj = t - (t / np) * np;
+        const int pi = pp[bi], qi = qq[bi], pj = pp[bj], qj = qq[bj];
+        const double ci = cc[bi], si = ss[bi], cj = cc[bj], sj = ss[bj];
+        if (si == 0.0 && sj == 0.0) continue;
+        const double a = A[pi * lda + pj];
+        const double b = (qj >= 0) ? A[pi * lda + qj] : 0.0;
+        const double c_ = (qi >= 0) ? A[qi * lda + pj] : 0.0;
+        const double d = (qi >= 0 && qj >= 0) ? A[qi * lda + qj] : 0.0;
+        const double a1 = ci * a - si * c_, b1 = ci * b - si * d;
+        const double c1 = si * a + ci * c_, d1 = si * b + ci * d;
+        A[pi * lda + pj] = cj * a1 - sj * b1;
+        if (qj >= 0) A[pi * lda + qj] = sj * a1 + cj * b1;
+        if (qi >= 0) A[qi * lda + pj] = cj * c1 - sj * d1;
+        if (qi >= 0 && qj >= 0) A[qi * lda + qj] = sj * c1 + cj * d1;
       }
-      __syncthreads();
-      // columns: A <- A J, U <- U J
       for (int t = tid; t < np * k; t += nt) {
-        const int i = t / k, j = t - (t / k) * k;
-        const int q = qq[i];
-        if (q < 0 || ss[i] == 0.0) continue;
-        const int p = pp[i];
-        const double c = cc[i], s = ss[i];
-        const double ap = A[j * lda + p], aq = A[j * lda + q];
-        A[j * lda + p] = c * ap - s * aq;
-        A[j * lda + q] = s * ap + c * aq;
-        const double up = U[j * ldu + p], uq = U[j * ldu + q];
-        U[j * ldu + p] = c * up - s * uq;
-        U[j * ldu + q] = s * up + c * uq;
+        const int bi = t / k, r = t - (t / k) * k;
+        const int q = qq[bi];
+        if (q < 0 || ss[bi] == 0.0) continue;
+        const int p = pp[bi];
+        const double c = cc[bi], s = ss[bi];
+        const double up = U[r * ldu + p], uq = U[r * ldu + q];
+        U[r * ldu + p] = c * up - s * uq;
+        U[r * ldu + q] = s * up + c * uq;
       }
       __syncthreads();
     }
     ++sweeps;
-    const int any = *flag;
-    __syncthreads();
-    if (!any) break;
   }
+  __syncthreads();
   return sweeps;
 }
 
@@ -124,37 +143,29 @@ __device__ void sort_desc(const double* A, int lda, int k, double* vals, int* pe
 // where lo = small[S_GERSH] bounds the spectrum from below (filter != 0;
 // filter == 0 gives Bn_i = W v_i / ||W v_i||).
 // LDS: 3 k x k matrices (L, Tt, U) + vectors.
-__global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ gram_part,
-                                                  int nslices, double* __restrict__ small, int k,
-                                                  int r, int lam_off, int filter) {
+__global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, int k, int r,
+                                                  int lam_off, int filter) {
   extern __shared__ double sm[];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int kk = k * k;
   double* L = sm;                 // k x k
   double* M = L + kk;             // k x k
   double* U = M + kk;             // k x k
-  double* d = U + kk;             // k
-  double* vals = d + KMAX;        // k
-  double* cs = vals + KMAX;       // 3 * (KMAX/2 + 1)
+  double* d = U + kk;             // KMAX
+  double* vals = d + KMAX;        // KMAX
+  double* inv = vals + KMAX;      // KMAX
+  double* cs = inv + KMAX;        // 3 * (KMAX/2 + 1)
   int* perm = reinterpret_cast<int*>(cs + 3 * (KMAX / 2 + 1));
-  int* flag = perm + KMAX;  // [0] dropped count, [1] jacobi, [2] current column dropped
-  double* G = small + SL::GG;
-  double* T = small + SL::TG;
-  double* P = small + SL::PG;
-  // 1. reduce the slice partials (G, T, P contiguous per slice)
-  for (int t = tid; t < 3 * kk; t += nt) {
-    double acc = 0.0;
-    for (int s = 0; s < nslices; ++s) acc += gram_part[(int64_t)s * 3 * kk + t];
-    const int which = t / kk;
-    G[which * SL::kk + (t - which * kk)] = acc;  // slots GG, TG, PG (stride k inside)
-  }
-  __syncthreads();
-  __threadfence_block();
-  // 2. symmetrise, equilibrate: d_i = 1/sqrt(G_ii)
+  int* flag = perm + KMAX;  // [0] dropped count, [1] jacobi
+  const double* G = small + SL::GG;
+  const double* T = small + SL::TG;
+  const double* P = small + SL::PG;
+  // 1. equilibrate: d_i = 1/sqrt(G_ii); L = D G D (+ shift), M = D T D (symmetrised)
   for (int t = tid; t < k; t += nt) {
     const double g = G[t * k + t];
     d[t] = (g > 0.0) ? 1.0 / sqrt(g) : 1.0;
   }
+  if (tid == 0) { flag[0] = 0; flag[1] = 0; }
   __syncthreads();
   for (int t = tid; t < kk; t += nt) {
     const int i = t / k, j = t - (t / k) * k;
@@ -163,46 +174,28 @@ __global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ gra
     L[t] = gij * d[i] * d[j] + ((i == j) ? 1e-15 * k : 0.0);
     M[t] = tij * d[i] * d[j];
   }
-  if (tid == 0) { flag[0] = 0; flag[1] = 0; flag[2] = 0; }
   __syncthreads();
-  // symmetrised T and P are written back for the residual step
-  for (int t = tid; t < kk; t += nt) {
-    const int i = t / k, j = t - (t / k) * k;
-    if (i < j) {
-      const double tij = 0.5 * (T[i * k + j] + T[j * k + i]);
-      const double pij = 0.5 * (P[i * k + j] + P[j * k + i]);
-      T[i * k + j] = tij; T[j * k + i] = tij;
-      P[i * k + j] = pij; P[j * k + i] = pij;
-    }
-  }
-  // 3. Cholesky of the equilibrated G (lower, in L).  A column whose pivot
+  // 2. Cholesky of the equilibrated G (lower, in L).  A column whose pivot
   //    falls below 1e-14 (numerically dependent on the previous ones) is
   //    dropped: L_jj = 1 with a zero sub-column, so its orthogonalised
   //    direction is the tiny remainder and its Ritz value is ~0.
   for (int j = 0; j < k; ++j) {
-    if (tid == 0) {
-      const double piv = L[j * k + j];
-      if (!(piv > 1e-14)) {
-        L[j * k + j] = 1.0;
-        flag[0] += 1;
-        flag[2] = 1;
-      } else {
-        L[j * k + j] = sqrt(piv);
-        flag[2] = 0;
-      }
-    }
-    __syncthreads();
-    const double ljj = L[j * k + j];
-    const bool dropped = flag[2] != 0;
+    const double piv = L[j * k + j];
+    const bool dropped = !(piv > 1e-14);
+    const double ljj = dropped ? 1.0 : sqrt(piv);
     for (int i = j + 1 + tid; i < k; i += nt) L[i * k + j] = dropped ? 0.0 : L[i * k + j] / ljj;
     __syncthreads();
+    if (tid == 0) {
+      L[j * k + j] = ljj;
+      if (dropped) flag[0] += 1;
+    }
     for (int t = tid; t < kk; t += nt) {
       const int i = t / k, c = t - (t / k) * k;
       if (i > j && c > j && c <= i) L[i * k + c] -= L[i * k + j] * L[c * k + j];
     }
     __syncthreads();
   }
-  // 4. Tt = L^{-1} M L^{-T}: U = L^{-1} M column by column, then M = L^{-1} U^T.
+  // 3. Tt = L^{-1} M L^{-T}: U = L^{-1} M column by column, then M = L^{-1} U^T.
   for (int c = tid; c < k; c += nt) {
     for (int i = 0; i < k; ++i) {
       double v = M[i * k + c];
@@ -228,29 +221,40 @@ __global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ gra
     }
   }
   __syncthreads();
-  // 5. eigendecomposition of Tt
+  // 4. eigendecomposition of Tt
   const int sweeps = jacobi_eig(M, k, U, k, k, cs, flag + 1, 40);
   sort_desc(M, k, k, vals, perm);
-  // 6. S = D L^{-T} U_sorted: back substitution per column, written to small[S].
-  double* S = small + SL::S;
+  // 5. S = D L^{-T} U_sorted: back substitution per column (into M, sorted order)
   for (int c = tid; c < k; c += nt) {
     const int pc = perm[c];
     for (int i = k - 1; i >= 0; --i) {
       double v = U[i * k + pc];
-      for (int j = i + 1; j < k; ++j) v -= L[j * k + i] * M[j * k + pc];
-      M[i * k + pc] = v / L[i * k + i];
+      for (int j = i + 1; j < k; ++j) v -= L[j * k + i] * M[j * k + c];
+      M[i * k + c] = v / L[i * k + i];
     }
   }
   __syncthreads();
+  double* S = small + SL::S;
   for (int t = tid; t < kk; t += nt) {
     const int i = t / k, c = t - (t / k) * k;
-    S[i * KMAX + c] = d[i] * M[i * k + perm[c]];
+    const double v = d[i] * M[t];
+    M[t] = v;                      // M now holds S (k x k, stride k)
+    S[i * KMAX + c] = v;
+  }
+  // P into U (LDS) for the residual product
+  for (int t = tid; t < kk; t += nt) {
+    const int i = t / k, j = t - (t / k) * k;
+    U[t] = 0.5 * (P[i * k + j] + P[j * k + i]);
   }
   __syncthreads();
-  __threadfence_block();
-  // 7. Ritz residuals and filter norms per column c (s = S[:, c], ||v|| = 1):
-  //    ||W v||^2 = s^T P s, v^T W v = s^T T s = theta,
-  //    ||(W - cI) v||^2 = s^T P s - 2 c s^T T s + c^2.
+  // 6. Y = P S (into L), then s_c^T P s_c = ||W v_c||^2 per column.
+  for (int t = tid; t < kk; t += nt) {
+    const int i = t / k, c = t - (t / k) * k;
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += U[i * k + j] * M[j * k + c];
+    L[t] = acc;
+  }
+  __syncthreads();
   double* theta = small + SL::THETA;
   double* res = small + SL::RES;
   double scale = fmax(fabs(vals[0]), fabs(vals[k - 1]));
@@ -263,35 +267,27 @@ __global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ gra
     fc = 0.5 * (lo + thk);
     fe = fmax(0.5 * (thk - lo), 1e-300);
   }
+  const double gam = filter ? fmax(fabs(vals[0] - fc), fe) : scale;
   for (int c = tid; c < k; c += nt) {
-    double sps = 0.0, sts = 0.0;
-    for (int i = 0; i < k; ++i) {
-      double pi = 0.0, ti = 0.0;
-      for (int j = 0; j < k; ++j) {
-        const double sj = S[j * KMAX + c];
-        pi += P[i * k + j] * sj;
-        ti += T[i * k + j] * sj;
-      }
-      const double si = S[i * KMAX + c];
-      sps += si * pi;
-      sts += si * ti;
-    }
+    double sps = 0.0;
+    for (int i = 0; i < k; ++i) sps += M[i * k + c] * L[i * k + c];
     const double th = vals[c];
     theta[c] = th;
     res[c] = sqrt(fmax(sps - th * th, 0.0)) / scale;
-    // column scale of the next basis: the predicted norm ||(W - cI) v||, floored
-    // at 1e-7 of the filter's largest amplification (the prediction cancels
-    // below that level), so that no column is blown up by rounding noise.
-    const double nrm2 = filter ? (sps - 2.0 * fc * sts + fc * fc) : sps;
-    const double gam = filter ? fmax(fabs(vals[0] - fc), fe) : scale;
-    const double inv = 1.0 / fmax(sqrt(fmax(nrm2, 0.0)), 1e-7 * gam);
-    for (int i = 0; i < k; ++i) {
-      const double si = S[i * KMAX + c];
-      small[SL::MZ + i * KMAX + c] = si * inv;
-      small[SL::MB + i * KMAX + c] = -fc * si * inv;
-    }
+    // column scale of the next basis: the predicted norm ||(W - cI) v|| (with
+    // v^T W v = theta), floored at 1e-7 of the filter's largest amplification
+    // (the prediction cancels below that level) so that no column is blown up
+    // by rounding noise.
+    const double nrm2 = filter ? (sps - 2.0 * fc * th + fc * fc) : sps;
+    inv[c] = 1.0 / fmax(sqrt(fmax(nrm2, 0.0)), 1e-7 * gam);
   }
   __syncthreads();
+  for (int t = tid; t < kk; t += nt) {
+    const int i = t / k, c = t - (t / k) * k;
+    const double sv = M[t] * inv[c];
+    small[SL::MZ + i * KMAX + c] = sv;
+    small[SL::MB + i * KMAX + c] = -fc * sv;
+  }
   if (tid == 0) {
     double mr = 0.0;
     const int rk = r < k ? r : k;
@@ -313,6 +309,19 @@ __global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ gra
     for (int c = 0; c < k; ++c) bad |= !isfinite(vals[c]);
     if (bad) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 1.0);
   }
+}
+
+// Sums the per-slice Gram partials [B^T B, B^T Z, Z^T Z] into the GG/TG/PG
+// slots of `small` (one thread per entry, fixed summation order).
+__global__ __launch_bounds__(256) void k_sum_grams(const double* __restrict__ gram_part,
+                                                   int nslices, int k, double* __restrict__ small) {
+  const int kk = k * k;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * kk) return;
+  double acc = 0.0;
+  for (int s = 0; s < nslices; ++s) acc += gram_part[(int64_t)s * 3 * kk + t];
+  const int which = t / kk;
+  small[SL::GG + which * SL::kk + (t - which * kk)] = acc;
 }
 
 // Exact eigendecomposition of the n x n W (n <= KMAX) in one workgroup; the

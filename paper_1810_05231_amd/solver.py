@@ -145,6 +145,19 @@ class Solver:
         """Restart from X0 = 0, y0 = 0 on the data already on the device."""
         check(lib.proxsdp_reset(self._h), "proxsdp_reset")
 
+    def rank_path(self):
+        """[(iteration, new r, reason)] with reason 1 = rank test failed at
+        convergence, 2 = windowed residual test found no decrease."""
+        cnt = C.c_int32()
+        check(lib.proxsdp_rank_path(self._h, None, None, None, 0, C.byref(cnt)), "rank_path")
+        m = max(cnt.value, 1)
+        it = np.zeros(m, np.int32)
+        rk = np.zeros(m, np.int32)
+        why = np.zeros(m, np.int32)
+        p = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        check(lib.proxsdp_rank_path(self._h, p(it), p(rk), p(why), m, C.byref(cnt)), "rank_path")
+        return [(int(a), int(b), int(c)) for a, b, c in zip(it, rk, why)][:cnt.value]
+
     def debug(self) -> dict:
         """Internal device scalars (see proxsdp_debug_scalars)."""
         out = np.zeros(64 + 64)

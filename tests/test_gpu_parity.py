@@ -155,7 +155,36 @@ def test_solve_matches_oracle(torch_cuda, kind, n, seed, full):
     _say("  oracle", ref.iters, ref.r, ref.obj)
     cert = O.certificate(prob, X, y)
     _say("  cert", cert.rho_p, cert.rho_d, cert.rel_gap)
-    assert info["obj"] == pytest.approx(ref.obj, rel=1e-5)
     assert max(cert.rho_p, cert.rho_d) <= 2e-4
     assert cert.lambda_min_X >= -1e-9 * max(1.0, np.abs(X).max())
+    if kind == "maxcut":
+        assert info["obj"] == pytest.approx(ref.obj, rel=1e-5)
+    else:
+        # equipartition has no strictly feasible primal point (X 1 = 0 is forced),
+        # so a residual of 1e-4 fixes the objective only up to the primal-dual gap;
+        # both answers must lie within the gap band of the oracle's certificate.
+        ref_cert = O.certificate(prob, ref.X, ref.y)
+        band = max(1e-5, 2.0 * max(ref_cert.rel_gap, cert.rel_gap))
+        _say("  equip band", band, "rel diff", abs(info["obj"] - ref.obj) / abs(ref.obj))
+        assert abs(info["obj"] - ref.obj) <= band * abs(ref.obj)
+    s.close()
+
+
+@pytest.mark.parametrize("kind,n,seed", [("equip", 120, 4), ("maxcut", 150, 3)])
+def test_solve_trajectory_with_converged_eigensolves(torch_cuda, kind, n, seed):
+    """With every partial eigensolve converged (eig_strict), the GPU follows the
+    oracle's trajectory: same control decisions, same iterate."""
+    from paper_1810_05231_amd import Solver
+    _say("trajectory", kind, n, seed)
+    prob = I.maxcut(n, 0.05, seed) if kind == "maxcut" else I.equipartition(n, 0.05, seed)
+    s = Solver(prob, tol=1e-4, eig_strict=1, eig_tol=1e-11)
+    info = s.solve()
+    ref = O.solve(prob, tol=1e-4)
+    _say("  gpu", info["status_name"], info["iters"], info["r"], repr(info["obj"]), s.rank_path())
+    _say("  oracle", ref.iters, ref.r, repr(ref.obj), ref.rank_path)
+    assert info["status_name"] == "converged"
+    assert info["iters"] == ref.iters and info["r"] == ref.r
+    assert info["obj"] == pytest.approx(ref.obj, rel=1e-8)
+    X, y = s.solution(on_device=False)
+    assert np.abs(X - ref.X).max() <= 1e-6 * max(1.0, np.abs(ref.X).max())
     s.close()
