@@ -37,6 +37,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1)
+    ap.add_argument("--window", type=int, default=0, help="Algorithm 2 window l (0 = library default)")
+    ap.add_argument("--eig-rel", type=float, default=0.0, help="eigen accuracy factor (0 = default)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -59,7 +61,12 @@ def main():
     prob = I.maxcut(n, args.p, args.seed)
     log(f"instance {prob.name}: n={n} edges={prob.meta['edges']} ({time.perf_counter()-t0:.1f}s)")
     t0 = time.perf_counter()
-    s = Solver(prob, device=dev, tol=args.tol)
+    opts = dict(tol=args.tol)
+    if args.window:
+        opts["window"] = args.window
+    if args.eig_rel:
+        opts["eig_rel"] = args.eig_rel
+    s = Solver(prob, device=dev, **opts)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"create (preprocess + upload + first eigensolve): {setup_s:.2f}s, workspace "
@@ -98,6 +105,8 @@ def main():
             f"rho=({info['rho_p']:.2e},{info['rho_d']:.2e}) rank path {s.rank_path()}")
     ms_per_step = 1000.0 * sum(times) / len(times)
     last = infos[-1]
+    _, lam_f = s.factors()
+    rank_x = int(np.sum(lam_f > 1e-8 * max(lam_f.max(), 1e-300))) if lam_f.size else 0
     # roofline of the dominant kernel: the dense pass Z = W B (FP64 MFMA), bytes = 8 n^2 per launch
     pass_ms = sum(p[0] for p in profs)
     pass_cnt = sum(p[1] for p in profs)
@@ -145,7 +154,8 @@ def main():
             "n": n, "edges": int(prob.meta["edges"]), "tol": args.tol,
             "iters": last["iters"], "final_rank": last["r"], "passes": last["passes"],
             "obj": last["obj"], "rho_p": last["rho_p"], "rho_d": last["rho_d"],
-            "setup_s": round(setup_s, 3), "rank_path": s.rank_path(),
+            "setup_s": round(setup_s, 3), "rank_path": s.rank_path(), "rank_X": rank_x,
+            "window": args.window or 50,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

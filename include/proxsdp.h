@@ -112,6 +112,8 @@ typedef struct {
   int32_t eig_strict;   /* 1: every iteration repeats eigensolver rounds until the
                            kept Ritz pairs meet eig_tol (synchronises per round;
                            for verification), 0 (default): adaptive schedule    */
+  double eig_rel;       /* adaptive schedule: target relative Ritz residual
+                           max(eig_tol, eig_rel * max(rho_p, rho_d)) (default 0.05) */
 } proxsdp_options;
 
 /* ------------------------------------------------------------- info */

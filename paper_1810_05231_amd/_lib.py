@@ -48,7 +48,7 @@ class Options(C.Structure):
         ("r_max", C.c_int32), ("full_eig", C.c_int32), ("precision", C.c_int32),
         ("max_iters", C.c_int32), ("time_limit_s", C.c_double), ("row_scaling", C.c_int32),
         ("block", C.c_int32), ("eig_tol", C.c_double), ("max_passes", C.c_int32),
-        ("seed", C.c_int32), ("eig_strict", C.c_int32),
+        ("seed", C.c_int32), ("eig_strict", C.c_int32), ("eig_rel", C.c_double),
     ]
 
 

@@ -36,7 +36,8 @@ struct SL {
   static constexpr int TG = GG + kk;
   static constexpr int PG = TG + kk;
   static constexpr int SC = PG + kk;           // named scalars
-  static constexpr int TOTAL = SC + 64;
+  static constexpr int FR = SC + 64;           // reduced factor partials (FAC_RES + KMAX values)
+  static constexpr int TOTAL = FR + 2 * kk + MAX_R1 * KMAX + KMAX;
 };
 
 enum Scalar {

@@ -107,8 +107,13 @@ __global__ __launch_bounds__(256) void k_reduce_gram(const double* __restrict__ 
                                                      const double* __restrict__ B,
                                                      const double* __restrict__ Bprev, int npad,
                                                      int k, double* __restrict__ gram_part,
-                                                     int cheb, double cc, double ce, int grams) {
+                                                     int cheb, double cc, double ce, int grams,
+                                                     const double* __restrict__ filt) {
   extern __shared__ double sm[];
+  if (filt) {  // filter centre and half-width of the last Rayleigh-Ritz step (device)
+    cc = filt[0];
+    ce = filt[1];
+  }
   double* sB = sm;
   double* sZ = sm + SLICE * k;
   const int s = blockIdx.x;
@@ -324,13 +329,22 @@ __global__ __launch_bounds__(256) void k_write_w(double* __restrict__ W, int64_t
                                                  int rank1, int has_fin, FinArgs fin,
                                                  int tiles_side) {
   extern __shared__ double sm[];
-  const int ntiles = tiles_side * tiles_side;
-  if ((int)blockIdx.x >= ntiles) {
+  const int T = tiles_side;
+  const int npairs = T * (T + 1) / 2;
+  if ((int)blockIdx.x >= npairs) {
     if (has_fin) finalize_iteration(fin, small, dp, y, y_old, sm);
     return;
   }
-  const int I = blockIdx.x / tiles_side;
-  const int J = blockIdx.x - I * tiles_side;
+  // block -> tile pair (I, J), I <= J, row-major over the upper triangle of tiles
+  const int idx = blockIdx.x;
+  auto first = [&](int i) { return i * T - (i * (i - 1)) / 2; };
+  const double tt = 2.0 * T + 1.0;
+  int I = (int)((tt - sqrt(fmax(tt * tt - 8.0 * idx, 0.0))) * 0.5);
+  I = max(0, min(I, T - 1));
+  while (I + 1 < T && first(I + 1) <= idx) ++I;
+  while (I > 0 && first(I) > idx) --I;
+  const int J = I + (idx - first(I));
+  const int tile_id = I * T + J;
   const int a0 = I * TILE, b0 = J * TILE;
   const int nq = rank1 ? dp.n_r1 : 0;
   const int rr = r + nq;
@@ -384,18 +398,27 @@ __global__ __launch_bounds__(256) void k_write_w(double* __restrict__ W, int64_t
   }
   if (sparse) {
     __syncthreads();
-    const int t0 = dp.tile_ptr[blockIdx.x], t1 = dp.tile_ptr[blockIdx.x + 1];
+    const int t0 = dp.tile_ptr[tile_id], t1 = dp.tile_ptr[tile_id + 1];
     for (int t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
       const int it = dp.tile_item[t];
       sT[(it >> 8) * (TILE + 1) + (it & 255)] += dval[dp.tile_e[t]];
     }
   }
   __syncthreads();
+  // tile (I, J) row by row, then its transpose into tile (J, I): W is symmetric
+  // (V diag(lam) V^T, the rank-one terms and the mirrored pattern all are).
   const int c = lane;
   for (int q = 0; q < TILE / 4; ++q) {
     const int a = w + 4 * q;
     const int ga = a0 + a, gb = b0 + c;
     if (ga < n && gb < n) W[(int64_t)ga * ld + gb] = sT[a * (TILE + 1) + c];
+  }
+  if (I != J) {
+    for (int q = 0; q < TILE / 4; ++q) {
+      const int b = w + 4 * q;
+      const int gb = b0 + b, ga = a0 + c;
+      if (gb < n && ga < n) W[(int64_t)gb * ld + ga] = sT[c * (TILE + 1) + b];
+    }
   }
 }
 

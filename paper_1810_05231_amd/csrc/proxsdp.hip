@@ -118,6 +118,7 @@ int validate(const proxsdp_problem* pb, const proxsdp_options* o) {
     if (o->alpha < 0) return fail(PROXSDP_ERR_INVALID, "alpha must be >= 0");
     if (o->full_eig && pb->n > KMAX)
       return fail(PROXSDP_ERR_UNSUPPORTED, "full_eig needs n <= " + std::to_string(KMAX));
+    if (!(o->eig_rel > 0)) return fail(PROXSDP_ERR_INVALID, "eig_rel must be > 0");
     if (o->block && (o->block % 16 || o->block > KMAX))
       return fail(PROXSDP_ERR_INVALID, "block must be a multiple of 16 and <= 64");
   }
@@ -442,7 +443,7 @@ struct proxsdp_handle {
   int nsl = 1, nrow_blocks = 1, npat_blocks = 1;
   // device buffers
   double* W = nullptr;
-  double* B[2] = {nullptr, nullptr};
+  double* B[3] = {nullptr, nullptr, nullptr};
   int bcur = 0;
   double* Z = nullptr;
   double* part = nullptr;
@@ -456,6 +457,7 @@ struct proxsdp_handle {
   // control
   int iters = 0, passes = 0, rank_updates = 0;
   int m_rounds = 2;
+  double eta = 1e-3;       // current relative Ritz residual target
   int status = PROXSDP_STATUS_RUNNING;
   std::vector<double> hist;
   std::vector<int> path_it, path_r, path_why;
@@ -490,6 +492,7 @@ static size_t carve(proxsdp_handle* H, void* ws) {
   H->W = c.take<double>((size_t)npad * npad);
   H->B[0] = c.take<double>((size_t)npad * H->k_cap);
   H->B[1] = c.take<double>((size_t)npad * H->k_cap);
+  H->B[2] = c.take<double>((size_t)npad * H->k_cap);
   H->Z = c.take<double>((size_t)npad * H->k_cap);
   H->part = c.take<double>((size_t)H->ch.nchunks * npad * H->k_cap);
   H->gram_part = c.take<double>((size_t)H->nsl * 3 * H->k_cap * H->k_cap);
@@ -634,20 +637,27 @@ static void launch_block(const double* W, int64_t ld, int n, int npad, const dou
 
 static void launch_reduce(const double* part, int nchunks, double* Z, const double* B,
                           const double* Bprev, int npad, int k, double* gram_part, int cheb,
-                          double cc, double ce, bool grams, hipStream_t st) {
+                          double cc, double ce, bool grams, hipStream_t st,
+                          const double* filt = nullptr) {
   const size_t lds = 2 * (size_t)SLICE * k * sizeof(double);
   hipLaunchKernelGGL(k_reduce_gram, dim3(n_slices(npad)), dim3(256), lds, st, part, nchunks, Z, B,
-                     Bprev, npad, k, gram_part, cheb, cc, ce, grams ? 1 : 0);
+                     Bprev, npad, k, gram_part, cheb, cc, ce, grams ? 1 : 0, filt);
 }
 
+#ifndef PROXSDP_RR_THREADS
+#define PROXSDP_RR_THREADS 256
+#endif
+
+// jac_tol: relative off-diagonal level at which the Jacobi sweeps stop.
 static void launch_rr(const double* gram_part, int nsl, double* small, int k, int r, int lam_off,
-                      int filter, hipStream_t st) {
+                      int filter, double jac_tol, hipStream_t st) {
   const int kk = k * k;
   hipLaunchKernelGGL(k_sum_grams, dim3((3 * kk + 255) / 256), dim3(256), 0, st, gram_part, nsl, k,
                      small);
-  const size_t lds = (3 * (size_t)k * k + 3 * KMAX + 3 * (KMAX / 2 + 1)) * sizeof(double) +
+  const size_t lds = (3 * (size_t)k * (k + 1) + 3 * KMAX + 3 * (KMAX / 2 + 1)) * sizeof(double) +
                      (KMAX + 4) * sizeof(int);
-  hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(256), lds, st, small, k, r, lam_off, filter);
+  hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(PROXSDP_RR_THREADS), lds, st, small, k, r, lam_off,
+                     filter, jac_tol);
 }
 
 static void launch_rowwise(proxsdp_handle* H, const double* B, double* V, int r, const double* Vold,
@@ -661,7 +671,7 @@ static void launch_rowwise(proxsdp_handle* H, const double* B, double* V, int r,
 static void launch_full(proxsdp_handle* H, double* V, int r, const double* Vold, int r_old,
                         int lam_off) {
   const int n = H->n;
-  const size_t lds = (2 * (size_t)n * n + n + 3 * (KMAX / 2 + 1)) * sizeof(double) +
+  const size_t lds = (2 * (size_t)n * (n + 1) + n + 3 * (KMAX / 2 + 1)) * sizeof(double) +
                      (KMAX + 4) * sizeof(int);
   hipLaunchKernelGGL(k_full_eig, dim3(1), dim3(1024), lds, H->st, H->W, (int64_t)H->npad, n, V, r,
                      Vold, r_old, H->small, lam_off, H->dp.n_r1, H->dp.r1_u, H->npad, H->fac_part);
@@ -675,7 +685,7 @@ static void launch_write(proxsdp_handle* H, double* Wout, int64_t ld, const doub
   const size_t lds = ((size_t)TILE * (TILE + 1) + 2 * (size_t)TILE * (rrp + 1)) * sizeof(double);
   FinArgs f{};
   if (fin) f = *fin;
-  hipLaunchKernelGGL(k_write_w, dim3(ts * ts + (fin ? 1 : 0)), dim3(256), lds, H->st, Wout, ld,
+  hipLaunchKernelGGL(k_write_w, dim3(ts * (ts + 1) / 2 + (fin ? 1 : 0)), dim3(256), lds, H->st, Wout, ld,
                      H->n, V, KMAX, r, H->small, lam_off, H->dp, H->y, H->y_old, H->dval,
                      sparse ? 1 : 0, rank1 ? 1 : 0, fin ? 1 : 0, f, ts);
 }
@@ -697,18 +707,55 @@ static int x2_slot(int parity) { return SL::SC + S_X2 + parity; }
 static void eig_round(proxsdp_handle* H, int par, bool final_round) {
   hipStream_t st = H->st;
   const double* Bc = H->B[H->bcur];
-  double* Bn = H->B[1 - H->bcur];
+  const int nb = (H->bcur + 1) % 3;
+  double* Bn = H->B[nb];
   prof_mark(H, H->ev_pass, H->n_pass, true);
   launch_block(H->W, H->npad, H->n, H->npad, Bc, H->k, H->part, H->ch, true, st);
   prof_mark(H, H->ev_pass, H->n_pass, false);
   launch_reduce(H->part, H->ch.nchunks, H->Z, Bc, nullptr, H->npad, H->k, H->gram_part, 0, 0.0,
                 1.0, true, st);
-  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, st);
+  const double jac_tol = H->opt.eig_strict ? 1e-15 : std::max(1e-15, std::min(1e-6, 0.01 * H->eta));
+  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, jac_tol, st);
   if (final_round)
     launch_rowwise(H, Bc, H->V[par], H->r, H->V[1 - par], H->r_old, Bn, st);
   else
     launch_rowwise(H, Bc, nullptr, H->r, nullptr, 0, Bn, st);
-  H->bcur = 1 - H->bcur;
+  H->bcur = nb;
+  H->passes += 1;
+}
+
+// One iteration's partial eigensolve with m dense passes: m - 1 Chebyshev
+// filter passes (T_j((W - cI)/e) applied to the current basis by the
+// three-term recurrence, fused into the reduction of each pass; c, e from the
+// last Rayleigh-Ritz step) and one pass followed by Rayleigh-Ritz, the Ritz
+// factors V[par] and the next basis (degree-one filter of the Ritz vectors).
+static void eig_iteration(proxsdp_handle* H, int par, int m) {
+  hipStream_t st = H->st;
+  const double* filt = H->small + SL::SC + S_FILTC;
+  int prev = -1, cur = H->bcur;
+  for (int j = 0; j < m - 1; ++j) {
+    int nxt = 0;
+    while (nxt == cur || nxt == prev) ++nxt;
+    prof_mark(H, H->ev_pass, H->n_pass, true);
+    launch_block(H->W, H->npad, H->n, H->npad, H->B[cur], H->k, H->part, H->ch, true, st);
+    prof_mark(H, H->ev_pass, H->n_pass, false);
+    launch_reduce(H->part, H->ch.nchunks, H->B[nxt], H->B[cur], prev >= 0 ? H->B[prev] : nullptr,
+                  H->npad, H->k, H->gram_part, prev >= 0 ? 2 : 1, 0.0, 1.0, false, st, filt);
+    prev = cur;
+    cur = nxt;
+    H->passes += 1;
+  }
+  int nb = 0;
+  while (nb == cur) ++nb;
+  prof_mark(H, H->ev_pass, H->n_pass, true);
+  launch_block(H->W, H->npad, H->n, H->npad, H->B[cur], H->k, H->part, H->ch, true, st);
+  prof_mark(H, H->ev_pass, H->n_pass, false);
+  launch_reduce(H->part, H->ch.nchunks, H->Z, H->B[cur], nullptr, H->npad, H->k, H->gram_part, 0,
+                0.0, 1.0, true, st);
+  const double jac_tol = std::max(1e-15, std::min(1e-6, 0.01 * H->eta));
+  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, jac_tol, st);
+  launch_rowwise(H, H->B[cur], H->V[par], H->r, H->V[1 - par], H->r_old, H->B[nb], st);
+  H->bcur = nb;
   H->passes += 1;
 }
 
@@ -754,7 +801,7 @@ static void iterate_once(proxsdp_handle* H) {
     }
     eig_round(H, par, true);
   } else {
-    for (int rd = 0; rd < H->m_rounds; ++rd) eig_round(H, par, rd == H->m_rounds - 1);
+    eig_iteration(H, par, H->m_rounds);
   }
   // dual step
   hipLaunchKernelGGL(k_gather_dual, dim3(H->nrow_blocks), dim3(256), 0, st, H->dp, H->V[par],
@@ -778,10 +825,11 @@ static void set_rank(proxsdp_handle* H, int r_new, int why) {
   if (k_new != H->k) {
     // re-layout the basis with the new width: old columns kept, new ones random
     const int64_t cnt = (int64_t)H->npad * k_new;
+    const int nb = (H->bcur + 1) % 3;
     hipLaunchKernelGGL(k_fill_basis, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, H->st,
-                       H->B[1 - H->bcur], k_new, H->B[H->bcur], H->k, std::min(H->k, k_new), H->n,
+                       H->B[nb], k_new, H->B[H->bcur], H->k, std::min(H->k, k_new), H->n,
                        H->npad, (uint32_t)(H->opt.seed * 7919 + H->rank_updates));
-    H->bcur = 1 - H->bcur;
+    H->bcur = nb;
     H->k = k_new;
   }
 }
@@ -861,7 +909,8 @@ static int control(proxsdp_handle* H) {
   // accuracy schedule of the partial eigensolve: relative Ritz residual target
   // tied to the current residual level (summable errors, Section 3.2)
   if (!H->full) {
-    const double eta = std::max(H->opt.eig_tol, 0.05 * std::max(rho_p, rho_d));
+    const double eta = std::max(H->opt.eig_tol, H->opt.eig_rel * std::max(rho_p, rho_d));
+    H->eta = eta;
     double worst = 0;
     for (auto& x : recs) worst = std::max(worst, x.maxres);
     if (worst > eta && H->m_rounds < H->opt.max_passes) H->m_rounds += 1;
@@ -896,6 +945,7 @@ static int init_state(proxsdp_handle* H) {
   zero(H->W, (size_t)H->npad * H->npad, st);
   zero(H->B[0], (size_t)H->npad * H->k_cap, st);
   zero(H->B[1], (size_t)H->npad * H->k_cap, st);
+  zero(H->B[2], (size_t)H->npad * H->k_cap, st);
   zero(H->Z, (size_t)H->npad * H->k_cap, st);
   zero(H->small, SL::TOTAL, st);
   zero(H->V[0], (size_t)H->npad * KMAX, st);
@@ -915,6 +965,7 @@ static int init_state(proxsdp_handle* H) {
   H->passes = 0;
   H->rank_updates = 0;
   H->m_rounds = 2;
+  H->eta = 1e-3;
   H->status = PROXSDP_STATUS_RUNNING;
   H->hist.clear();
   H->path_it.clear();
@@ -962,6 +1013,8 @@ int proxsdp_default_options(proxsdp_options* o) {
   o->eig_tol = 1e-10;
   o->max_passes = 8;
   o->seed = 1;
+  o->eig_strict = 0;
+  o->eig_rel = 0.05;
   return PROXSDP_OK;
 }
 
@@ -1215,7 +1268,7 @@ int proxsdp_project_psd(const void* S, int32_t n, int64_t lds, int32_t r, int32_
   const double* Sd = static_cast<const double*>(S);
   const int lam_off = lam_slot(0);
   if (H.full) {
-    const size_t lds_b = (2 * (size_t)n * n + n + 3 * (KMAX / 2 + 1)) * sizeof(double) + (KMAX + 4) * sizeof(int);
+    const size_t lds_b = (2 * (size_t)n * (n + 1) + n + 3 * (KMAX / 2 + 1)) * sizeof(double) + (KMAX + 4) * sizeof(int);
     hipLaunchKernelGGL(k_full_eig, dim3(1), dim3(1024), lds_b, st, Sd, lds, n, H.V[0], re, H.V[0], 0,
                        H.small, lam_off, 0, (const double*)nullptr, H.npad, H.fac_part);
   } else {
@@ -1235,7 +1288,7 @@ int proxsdp_project_psd(const void* S, int32_t n, int64_t lds, int32_t r, int32_
       launch_block(Sd, lds, n, H.npad, Bc, k, H.part, H.ch, false, st);
       launch_reduce(H.part, H.ch.nchunks, H.Z, Bc, nullptr, H.npad, k, H.gram_part, 0, 0.0, 1.0, true, st);
       const int n_unshifted = 6;
-      launch_rr(H.gram_part, H.nsl, H.small, k, re, lam_off, rd >= n_unshifted ? 1 : 0, st);
+      launch_rr(H.gram_part, H.nsl, H.small, k, re, lam_off, rd >= n_unshifted ? 1 : 0, 1e-15, st);
       if (rd == n_unshifted - 1) hipLaunchKernelGGL(k_set_lower_bound, dim3(1), dim3(64), 0, st, H.small);
       launch_rowwise(&H, Bc, H.V[0], re, H.V[0], 0, Bn, st);
       const bool check = (rd % 4 == 3) || rd == max_rounds - 1;

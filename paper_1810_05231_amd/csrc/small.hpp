@@ -28,7 +28,7 @@ __device__ inline int rr_player(int pos, int rnd, int kk) {
 // `cs` is LDS scratch of 3 (KMAX/2 + 1) doubles; `red` of 2 doubles.
 // Returns the number of sweeps.
 __device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double* cs, int* flag,
-                          int max_sweeps) {
+                          int max_sweeps, double tol_off = 1e-15) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int t = tid; t < k * k; t += nt) {
     const int i = t / k, j = t - (t / k) * k;
@@ -61,7 +61,7 @@ __device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double*
       atomicAdd(&offd[1], dg);
     }
     __syncthreads();
-    if (!(offd[0] > 1e-30 * offd[1]) || !(offd[0] > 1e-300)) break;
+    if (!(offd[0] > tol_off * tol_off * offd[1]) || !(offd[0] > 1e-300)) break;
     for (int rnd = 0; rnd < kk - 1; ++rnd) {
       for (int i = tid; i < np; i += nt) {
         int p = rr_player(i, rnd, kk), q = rr_player(kk - 1 - i, rnd, kk);
@@ -116,17 +116,26 @@ __device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double*
 }
 
 // Sorts eigenvalues (diagonal of A) decreasingly: writes values to `vals`
-// and the permutation to `perm` (single thread; k <= KMAX).
+// and the permutation to `perm`.  Rank sort: thread i counts the entries that
+// precede it (larger, or equal with a smaller index), k <= KMAX.
 __device__ void sort_desc(const double* A, int lda, int k, double* vals, int* perm) {
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < k; ++i) { perm[i] = i; vals[i] = A[i * lda + i]; }
-    for (int i = 1; i < k; ++i) {
-      const double v = vals[i];
-      const int p = perm[i];
-      int j = i - 1;
-      while (j >= 0 && vals[j] < v) { vals[j + 1] = vals[j]; perm[j + 1] = perm[j]; --j; }
-      vals[j + 1] = v;
-      perm[j + 1] = p;
+  // identity first, so that a non-finite value (flagged elsewhere) can only
+  // leave a valid index behind
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    vals[i] = A[i * lda + i];
+    perm[i] = i;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const double v = A[i * lda + i];
+    int rank = 0;
+    for (int j = 0; j < k; ++j) {
+      const double u = A[j * lda + j];
+      rank += (u > v) || (u == v && j < i);
+    }
+    if (rank < k) {
+      vals[rank] = v;
+      perm[rank] = i;
     }
   }
   __syncthreads();
@@ -143,15 +152,31 @@ __device__ void sort_desc(const double* A, int lda, int k, double* vals, int* pe
 // where lo = small[S_GERSH] bounds the spectrum from below (filter != 0;
 // filter == 0 gives Bn_i = W v_i / ||W v_i||).
 // LDS: 3 k x k matrices (L, Tt, U) + vectors.
+// Dot product of length n over LDS with four independent accumulators
+// (keeps several LDS loads in flight).
+__device__ inline double lds_dot(const double* a, int sa, const double* b, int sb, int n) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = 0;
+  for (; j + 3 < n; j += 4) {
+    s0 += a[(j + 0) * sa] * b[(j + 0) * sb];
+    s1 += a[(j + 1) * sa] * b[(j + 1) * sb];
+    s2 += a[(j + 2) * sa] * b[(j + 2) * sb];
+    s3 += a[(j + 3) * sa] * b[(j + 3) * sb];
+  }
+  for (; j < n; ++j) s0 += a[j * sa] * b[j * sb];
+  return (s0 + s1) + (s2 + s3);
+}
+
 __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, int k, int r,
-                                                  int lam_off, int filter) {
+                                                  int lam_off, int filter, double jac_tol) {
   extern __shared__ double sm[];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int kk = k * k;
-  double* L = sm;                 // k x k
-  double* M = L + kk;             // k x k
-  double* U = M + kk;             // k x k
-  double* d = U + kk;             // KMAX
+  const int ld = k + 1;           // odd LDS row stride: column walks hit distinct banks
+  double* L = sm;                 // k x ld
+  double* M = L + k * ld;         // k x ld
+  double* U = M + k * ld;         // k x ld
+  double* d = U + k * ld;         // KMAX
   double* vals = d + KMAX;        // KMAX
   double* inv = vals + KMAX;      // KMAX
   double* cs = inv + KMAX;        // 3 * (KMAX/2 + 1)
@@ -171,8 +196,8 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
     const int i = t / k, j = t - (t / k) * k;
     const double tij = 0.5 * (T[i * k + j] + T[j * k + i]);
     const double gij = 0.5 * (G[i * k + j] + G[j * k + i]);
-    L[t] = gij * d[i] * d[j] + ((i == j) ? 1e-15 * k : 0.0);
-    M[t] = tij * d[i] * d[j];
+    L[i * ld + j] = gij * d[i] * d[j] + ((i == j) ? 1e-15 * k : 0.0);
+    M[i * ld + j] = tij * d[i] * d[j];
   }
   __syncthreads();
   // 2. Cholesky of the equilibrated G (lower, in L).  A column whose pivot
@@ -180,79 +205,77 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
   //    dropped: L_jj = 1 with a zero sub-column, so its orthogonalised
   //    direction is the tiny remainder and its Ritz value is ~0.
   for (int j = 0; j < k; ++j) {
-    const double piv = L[j * k + j];
+    const double piv = L[j * ld + j];
     const bool dropped = !(piv > 1e-14);
     const double ljj = dropped ? 1.0 : sqrt(piv);
-    for (int i = j + 1 + tid; i < k; i += nt) L[i * k + j] = dropped ? 0.0 : L[i * k + j] / ljj;
+    for (int i = j + 1 + tid; i < k; i += nt) L[i * ld + j] = dropped ? 0.0 : L[i * ld + j] / ljj;
     __syncthreads();
     if (tid == 0) {
-      L[j * k + j] = ljj;
+      L[j * ld + j] = ljj;
       if (dropped) flag[0] += 1;
     }
-    for (int t = tid; t < kk; t += nt) {
-      const int i = t / k, c = t - (t / k) * k;
-      if (i > j && c > j && c <= i) L[i * k + c] -= L[i * k + j] * L[c * k + j];
+    // trailing update of the lower triangle (i >= c > j), enumerated directly
+    const int rem = k - 1 - j;
+    for (int t = tid; t < rem * rem; t += nt) {
+      const int i = j + 1 + t / rem, c = j + 1 + (t - (t / rem) * rem);
+      if (c <= i) L[i * ld + c] -= L[i * ld + j] * L[c * ld + j];
     }
     __syncthreads();
   }
   // 3. Tt = L^{-1} M L^{-T}: U = L^{-1} M column by column, then M = L^{-1} U^T.
   for (int c = tid; c < k; c += nt) {
     for (int i = 0; i < k; ++i) {
-      double v = M[i * k + c];
-      for (int j = 0; j < i; ++j) v -= L[i * k + j] * U[j * k + c];
-      U[i * k + c] = v / L[i * k + i];
+      const double v = M[i * ld + c] - lds_dot(L + i * ld, 1, U + c, ld, i);
+      U[i * ld + c] = v / L[i * ld + i];
     }
   }
   __syncthreads();
   for (int c = tid; c < k; c += nt) {
     for (int i = 0; i < k; ++i) {
-      double v = U[c * k + i];
-      for (int j = 0; j < i; ++j) v -= L[i * k + j] * M[j * k + c];
-      M[i * k + c] = v / L[i * k + i];
+      const double v = U[c * ld + i] - lds_dot(L + i * ld, 1, M + c, ld, i);
+      M[i * ld + c] = v / L[i * ld + i];
     }
   }
   __syncthreads();
   for (int t = tid; t < kk; t += nt) {
     const int i = t / k, j = t - (t / k) * k;
     if (i < j) {
-      const double v = 0.5 * (M[i * k + j] + M[j * k + i]);
-      M[i * k + j] = v;
-      M[j * k + i] = v;
+      const double v = 0.5 * (M[i * ld + j] + M[j * ld + i]);
+      M[i * ld + j] = v;
+      M[j * ld + i] = v;
     }
   }
   __syncthreads();
   // 4. eigendecomposition of Tt
-  const int sweeps = jacobi_eig(M, k, U, k, k, cs, flag + 1, 40);
-  sort_desc(M, k, k, vals, perm);
-  // 5. S = D L^{-T} U_sorted: back substitution per column (into M, sorted order)
+  const int sweeps = jacobi_eig(M, ld, U, ld, k, cs, flag + 1, 40, jac_tol);
+  sort_desc(M, ld, k, vals, perm);
+  // 5. S = D L^{-T} U_sorted: back substitution per column (into L's upper
+  //    part is not possible: write into M, sorted column order)
   for (int c = tid; c < k; c += nt) {
     const int pc = perm[c];
     for (int i = k - 1; i >= 0; --i) {
-      double v = U[i * k + pc];
-      for (int j = i + 1; j < k; ++j) v -= L[j * k + i] * M[j * k + c];
-      M[i * k + c] = v / L[i * k + i];
+      const double v = U[i * ld + pc] - lds_dot(L + (i + 1) * ld + i, ld, M + (i + 1) * ld + c, ld, k - 1 - i);
+      M[i * ld + c] = v / L[i * ld + i];
     }
   }
   __syncthreads();
   double* S = small + SL::S;
   for (int t = tid; t < kk; t += nt) {
     const int i = t / k, c = t - (t / k) * k;
-    const double v = d[i] * M[t];
-    M[t] = v;                      // M now holds S (k x k, stride k)
+    const double v = d[i] * M[i * ld + c];
+    M[i * ld + c] = v;             // M now holds S
     S[i * KMAX + c] = v;
   }
   // P into U (LDS) for the residual product
   for (int t = tid; t < kk; t += nt) {
     const int i = t / k, j = t - (t / k) * k;
-    U[t] = 0.5 * (P[i * k + j] + P[j * k + i]);
+    U[i * ld + j] = 0.5 * (P[i * k + j] + P[j * k + i]);
   }
   __syncthreads();
   // 6. Y = P S (into L), then s_c^T P s_c = ||W v_c||^2 per column.
   for (int t = tid; t < kk; t += nt) {
     const int i = t / k, c = t - (t / k) * k;
-    double acc = 0.0;
-    for (int j = 0; j < k; ++j) acc += U[i * k + j] * M[j * k + c];
-    L[t] = acc;
+    L[i * ld + c] = lds_dot(U + i * ld, 1, M + c, ld, k);
   }
   __syncthreads();
   double* theta = small + SL::THETA;
@@ -269,8 +292,7 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
   }
   const double gam = filter ? fmax(fabs(vals[0] - fc), fe) : scale;
   for (int c = tid; c < k; c += nt) {
-    double sps = 0.0;
-    for (int i = 0; i < k; ++i) sps += M[i * k + c] * L[i * k + c];
+    const double sps = lds_dot(M + c, ld, L + c, ld, k);
     const double th = vals[c];
     theta[c] = th;
     res[c] = sqrt(fmax(sps - th * th, 0.0)) / scale;
@@ -284,7 +306,7 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
   __syncthreads();
   for (int t = tid; t < kk; t += nt) {
     const int i = t / k, c = t - (t / k) * k;
-    const double sv = M[t] * inv[c];
+    const double sv = M[i * ld + c] * inv[c];
     small[SL::MZ + i * KMAX + c] = sv;
     small[SL::MB + i * KMAX + c] = -fc * sv;
   }
@@ -319,6 +341,7 @@ __global__ __launch_bounds__(256) void k_sum_grams(const double* __restrict__ gr
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 3 * kk) return;
   double acc = 0.0;
+#pragma unroll 8
   for (int s = 0; s < nslices; ++s) acc += gram_part[(int64_t)s * 3 * kk + t];
   const int which = t / kk;
   small[SL::GG + which * SL::kk + (t - which * kk)] = acc;
@@ -328,7 +351,7 @@ __global__ __launch_bounds__(256) void k_sum_grams(const double* __restrict__ gr
 // top r eigenpairs become the factors (V row stride KMAX, lambda_+ at
 // lam_off), and the factor partials of the single slice are formed as in
 // k_rowwise (nslices = 1 downstream).
-__global__ __launch_bounds__(1024) void k_full_eig(const double* __restrict__ W, int64_t ld, int n,
+__global__ __launch_bounds__(1024) void k_full_eig(const double* __restrict__ W, int64_t ldw, int n,
                                                    double* __restrict__ V, int r,
                                                    const double* __restrict__ Vold, int r_old,
                                                    double* __restrict__ small, int lam_off,
@@ -336,23 +359,24 @@ __global__ __launch_bounds__(1024) void k_full_eig(const double* __restrict__ W,
                                                    int npad, double* __restrict__ fac_part) {
   extern __shared__ double sm[];
   const int tid = threadIdx.x, nt = blockDim.x;
-  double* A = sm;                  // n x n
-  double* U = A + n * n;           // n x n
-  double* vals = U + n * n;        // n
+  const int ld = n + 1;            // odd LDS stride
+  double* A = sm;                  // n x ld
+  double* U = A + n * ld;          // n x ld
+  double* vals = U + n * ld;       // n
   double* cs = vals + n;           // 2 (n/2 + 1) + ints
   int* perm = reinterpret_cast<int*>(cs + 3 * (KMAX / 2 + 1));
   int* flag = perm + KMAX;
   for (int t = tid; t < n * n; t += nt) {
     const int i = t / n, j = t - (t / n) * n;
-    A[t] = 0.5 * (W[(int64_t)i * ld + j] + W[(int64_t)j * ld + i]);
+    A[i * (n + 1) + j] = 0.5 * (W[(int64_t)i * ldw + j] + W[(int64_t)j * ldw + i]);
   }
   __syncthreads();
-  const int sweeps = jacobi_eig(A, n, U, n, n, cs, flag, 60);
-  sort_desc(A, n, n, vals, perm);
+  const int sweeps = jacobi_eig(A, ld, U, ld, n, cs, flag, 60);
+  sort_desc(A, ld, n, vals, perm);
   // factors
   for (int t = tid; t < n * r; t += nt) {
     const int i = t / r, c = t - (t / r) * r;
-    V[(int64_t)i * KMAX + c] = U[i * n + perm[c]];
+    V[(int64_t)i * KMAX + c] = U[i * ld + perm[c]];
   }
   double* theta = small + SL::THETA;
   for (int c = tid; c < n; c += nt) {
@@ -378,15 +402,15 @@ __global__ __launch_bounds__(1024) void k_full_eig(const double* __restrict__ W,
     double acc = 0.0;
     if (t < n1) {
       const int a = t / r, b = t - (t / r) * r;
-      for (int i = 0; i < n; ++i) acc += U[i * n + perm[a]] * U[i * n + perm[b]];
+      for (int i = 0; i < n; ++i) acc += U[i * ld + perm[a]] * U[i * ld + perm[b]];
     } else if (t < n1 + n2) {
       const int e = t - n1;
       const int a = e / r_old, b = e - (e / r_old) * r_old;
-      for (int i = 0; i < n; ++i) acc += U[i * n + perm[a]] * Vold[(int64_t)i * KMAX + b];
+      for (int i = 0; i < n; ++i) acc += U[i * ld + perm[a]] * Vold[(int64_t)i * KMAX + b];
     } else {
       const int e = t - n1 - n2;
       const int q = e / r, a = e - (e / r) * r;
-      for (int i = 0; i < n; ++i) acc += r1_u[(int64_t)q * npad + i] * U[i * n + perm[a]];
+      for (int i = 0; i < n; ++i) acc += r1_u[(int64_t)q * npad + i] * U[i * ld + perm[a]];
     }
     fac_part[t] = acc;
   }

@@ -52,7 +52,7 @@ __device__ inline double factor_entry(const double* V, const double* lam, int r,
 }
 
 __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double* __restrict__ V,
-                                                     int r, const double* __restrict__ small,
+                                                     int r, double* __restrict__ small,
                                                      int lam_off, const double* __restrict__ fac_part,
                                                      int nslices, int r_old,
                                                      double* __restrict__ y,
@@ -61,6 +61,19 @@ __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double
                                                      double* __restrict__ MX_old,
                                                      double* __restrict__ row_part) {
   __shared__ double red[16];
+  // reduce the factor partials over the slices for the finalisation:
+  // [V^T V (r x r) | V^T Vold (r x r_old)] -> small[FR ..], residuals -> small[FR + FAC_RES ..]
+  {
+    const int nfac = r * r + r * r_old;
+    const int gsz = gridDim.x * blockDim.x;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nfac + r; t += gsz) {
+      const int src = (t < nfac) ? t : FAC_RES + (t - nfac);
+      double acc = 0.0;
+#pragma unroll 8
+      for (int s = 0; s < nslices; ++s) acc += fac_part[(int64_t)s * FAC_STRIDE + src];
+      small[SL::FR + src] = acc;
+    }
+  }
   const double* lam = small + lam_off;
   const double alpha = small[SL::SC + S_ALPHA];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -180,9 +193,9 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
   const double* lam0 = small + f.lam_old;
   const int r = f.r, r0 = f.r_old;
   double x2 = 0.0, x01 = 0.0;
+  const double* fr = small + SL::FR;   // slice sums formed by the dual-step kernel
   for (int t = tid; t < r * r + r * r0; t += nt) {
-    double g = 0.0;
-    for (int s = 0; s < f.nslices; ++s) g += f.fac_part[(int64_t)s * FAC_STRIDE + t];
+    const double g = fr[t];
     if (t < r * r) {
       const int a = t / r, b = t - (t / r) * r;
       x2 += lam[a] * lam[b] * g * g;
@@ -223,11 +236,7 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     int npos = 0;
     while (npos < r && theta[npos] > 0.0) ++npos;
     const int nchk = npos > 0 ? npos : (r > 0 ? 1 : 0);
-    for (int c = tid; c < nchk; c += nt) {
-      double acc = 0.0;
-      for (int s = 0; s < f.nslices; ++s) acc += f.fac_part[(int64_t)s * FAC_STRIDE + FAC_RES + c];
-      worst = fmax(worst, sqrt(acc) / scale);
-    }
+    for (int c = tid; c < nchk; c += nt) worst = fmax(worst, sqrt(fr[FAC_RES + c]) / scale);
     for (int o = 32; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o));
     __syncthreads();
     if ((tid & 63) == 0) red[tid >> 6] = worst;
