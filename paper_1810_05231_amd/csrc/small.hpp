@@ -80,32 +80,66 @@ __device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double*
         cc[i] = c; ss[i] = s; pp[i] = p; qq[i] = (q < k) ? q : -1;
       }
       __syncthreads();
-      // A <- J^T A J blockwise; U <- U J
-      for (int t = tid; t < np * np; t += nt) {
-        const int bi = t / np, bj = t - (t / np) * np;
-        const int pi = pp[bi], qi = qq[bi], pj = pp[bj], qj = qq[bj];
-        const double ci = cc[bi], si = ss[bi], cj = cc[bj], sj = ss[bj];
-        if (si == 0.0 && sj == 0.0) continue;
-        const double a = A[pi * lda + pj];
-        const double b = (qj >= 0) ? A[pi * lda + qj] : 0.0;
-        const double c_ = (qi >= 0) ? A[qi * lda + pj] : 0.0;
-        const double d = (qi >= 0 && qj >= 0) ? A[qi * lda + qj] : 0.0;
-        const double a1 = ci * a - si * c_, b1 = ci * b - si * d;
-        const double c1 = si * a + ci * c_, d1 = si * b + ci * d;
-        A[pi * lda + pj] = cj * a1 - sj * b1;
-        if (qj >= 0) A[pi * lda + qj] = sj * a1 + cj * b1;
-        if (qi >= 0) A[qi * lda + pj] = cj * c1 - sj * d1;
-        if (qi >= 0 && qj >= 0) A[qi * lda + qj] = sj * c1 + cj * d1;
-      }
-      for (int t = tid; t < np * k; t += nt) {
-        const int bi = t / k, r = t - (t / k) * k;
-        const int q = qq[bi];
-        if (q < 0 || ss[bi] == 0.0) continue;
-        const int p = pp[bi];
-        const double c = cc[bi], s = ss[bi];
-        const double up = U[r * ldu + p], uq = U[r * ldu + q];
-        U[r * ldu + p] = c * up - s * uq;
-        U[r * ldu + q] = s * up + c * uq;
+      // A <- J^T A J blockwise; U <- U J.  A thread keeps one row pair (its
+      // rotation in registers) and handles column pairs / rows in batches of
+      // four: all loads, then the arithmetic, then all stores, so the LDS
+      // latency is paid once per batch.
+      {
+        const int groups = nt / np;
+        const int bi = tid % np, g0 = tid / np;
+        if (g0 < groups) {
+          const int pi = pp[bi], qi = qq[bi];
+          const double ci = cc[bi], si = ss[bi];
+          for (int b0 = g0; b0 < np; b0 += 4 * groups) {
+            double a[4], b[4], c_[4], d[4], cj[4], sj[4];
+            int pj[4], qj[4];
+            bool on[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int bj = b0 + u * groups;
+              on[u] = bj < np;
+              const int bjj = on[u] ? bj : bi;
+              pj[u] = pp[bjj];
+              qj[u] = qq[bjj];
+              cj[u] = cc[bjj];
+              sj[u] = ss[bjj];
+              on[u] = on[u] && !(si == 0.0 && sj[u] == 0.0);
+              a[u] = A[pi * lda + pj[u]];
+              b[u] = (qj[u] >= 0) ? A[pi * lda + qj[u]] : 0.0;
+              c_[u] = (qi >= 0) ? A[qi * lda + pj[u]] : 0.0;
+              d[u] = (qi >= 0 && qj[u] >= 0) ? A[qi * lda + qj[u]] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (!on[u]) continue;
+              const double a1 = ci * a[u] - si * c_[u], b1 = ci * b[u] - si * d[u];
+              const double c1 = si * a[u] + ci * c_[u], d1 = si * b[u] + ci * d[u];
+              A[pi * lda + pj[u]] = cj[u] * a1 - sj[u] * b1;
+              if (qj[u] >= 0) A[pi * lda + qj[u]] = sj[u] * a1 + cj[u] * b1;
+              if (qi >= 0) A[qi * lda + pj[u]] = cj[u] * c1 - sj[u] * d1;
+              if (qi >= 0 && qj[u] >= 0) A[qi * lda + qj[u]] = sj[u] * c1 + cj[u] * d1;
+            }
+          }
+          if (qi >= 0 && si != 0.0) {
+            for (int r0 = g0; r0 < k; r0 += 4 * groups) {
+              double up[4], uq[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int r = r0 + u * groups;
+                up[u] = (r < k) ? U[r * ldu + pi] : 0.0;
+                uq[u] = (r < k) ? U[r * ldu + qi] : 0.0;
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int r = r0 + u * groups;
+                if (r < k) {
+                  U[r * ldu + pi] = ci * up[u] - si * uq[u];
+                  U[r * ldu + qi] = si * up[u] + ci * uq[u];
+                }
+              }
+            }
+          }
+        }
       }
       __syncthreads();
     }
@@ -214,26 +248,51 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
       L[j * ld + j] = ljj;
       if (dropped) flag[0] += 1;
     }
-    // trailing update of the lower triangle (i >= c > j), enumerated directly
+    // trailing update of the lower triangle (i >= c > j), four entries per batch
     const int rem = k - 1 - j;
-    for (int t = tid; t < rem * rem; t += nt) {
-      const int i = j + 1 + t / rem, c = j + 1 + (t - (t / rem) * rem);
-      if (c <= i) L[i * ld + c] -= L[i * ld + j] * L[c * ld + j];
+    for (int t0 = tid; t0 < rem * rem; t0 += 4 * nt) {
+      double lij[4], lcj[4], lic[4];
+      int pos[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + u * nt;
+        const int i = j + 1 + t / rem, c = j + 1 + (t - (t / rem) * rem);
+        const bool on = t < rem * rem && c <= i;
+        pos[u] = on ? i * ld + c : -1;
+        lij[u] = on ? L[i * ld + j] : 0.0;
+        lcj[u] = on ? L[c * ld + j] : 0.0;
+        lic[u] = on ? L[i * ld + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (pos[u] >= 0) L[pos[u]] = lic[u] - lij[u] * lcj[u];
     }
     __syncthreads();
   }
   // 3. Tt = L^{-1} M L^{-T}: U = L^{-1} M column by column, then M = L^{-1} U^T.
-  for (int c = tid; c < k; c += nt) {
-    for (int i = 0; i < k; ++i) {
-      const double v = M[i * ld + c] - lds_dot(L + i * ld, 1, U + c, ld, i);
-      U[i * ld + c] = v / L[i * ld + i];
+  //    Four lanes per column share each dot product (shuffle reduction).
+  {
+    const int c = tid >> 2, part = tid & 3;
+    if (c < k) {
+      for (int i = 0; i < k; ++i) {
+        double sacc = 0.0;
+        for (int j = part; j < i; j += 4) sacc += L[i * ld + j] * U[j * ld + c];
+        sacc += __shfl_xor(sacc, 1);
+        sacc += __shfl_xor(sacc, 2);
+        const double v = (M[i * ld + c] - sacc) / L[i * ld + i];
+        if (part == 0) U[i * ld + c] = v;
+      }
     }
-  }
-  __syncthreads();
-  for (int c = tid; c < k; c += nt) {
-    for (int i = 0; i < k; ++i) {
-      const double v = U[c * ld + i] - lds_dot(L + i * ld, 1, M + c, ld, i);
-      M[i * ld + c] = v / L[i * ld + i];
+    __syncthreads();
+    if (c < k) {
+      for (int i = 0; i < k; ++i) {
+        double sacc = 0.0;
+        for (int j = part; j < i; j += 4) sacc += L[i * ld + j] * M[j * ld + c];
+        sacc += __shfl_xor(sacc, 1);
+        sacc += __shfl_xor(sacc, 2);
+        const double v = (U[c * ld + i] - sacc) / L[i * ld + i];
+        if (part == 0) M[i * ld + c] = v;
+      }
     }
   }
   __syncthreads();
@@ -251,11 +310,18 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
   sort_desc(M, ld, k, vals, perm);
   // 5. S = D L^{-T} U_sorted: back substitution per column (into L's upper
   //    part is not possible: write into M, sorted column order)
-  for (int c = tid; c < k; c += nt) {
-    const int pc = perm[c];
-    for (int i = k - 1; i >= 0; --i) {
-      const double v = U[i * ld + pc] - lds_dot(L + (i + 1) * ld + i, ld, M + (i + 1) * ld + c, ld, k - 1 - i);
-      M[i * ld + c] = v / L[i * ld + i];
+  {
+    const int c = tid >> 2, part = tid & 3;
+    if (c < k) {
+      const int pc = perm[c];
+      for (int i = k - 1; i >= 0; --i) {
+        double sacc = 0.0;
+        for (int j = i + 1 + part; j < k; j += 4) sacc += L[j * ld + i] * M[j * ld + c];
+        sacc += __shfl_xor(sacc, 1);
+        sacc += __shfl_xor(sacc, 2);
+        const double v = (U[i * ld + pc] - sacc) / L[i * ld + i];
+        if (part == 0) M[i * ld + c] = v;
+      }
     }
   }
   __syncthreads();
@@ -272,10 +338,22 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
     U[i * ld + j] = 0.5 * (P[i * k + j] + P[j * k + i]);
   }
   __syncthreads();
-  // 6. Y = P S (into L), then s_c^T P s_c = ||W v_c||^2 per column.
-  for (int t = tid; t < kk; t += nt) {
-    const int i = t / k, c = t - (t / k) * k;
-    L[i * ld + c] = lds_dot(U + i * ld, 1, M + c, ld, k);
+  // 6. Y = P S (into L) on MFMA f64 16x16x4, then s_c^T P s_c = ||W v_c||^2.
+  {
+    typedef double d4v __attribute__((ext_vector_type(4)));
+    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    const int m = lane & 15, kq = lane >> 4, kb = k / 16;
+    for (int blk = wave; blk < kb * kb; blk += nw) {
+      const int a0 = (blk / kb) * 16, b0 = (blk - (blk / kb) * kb) * 16;
+      d4v acc = {0.0, 0.0, 0.0, 0.0};
+      for (int q0 = 0; q0 < k; q0 += 4) {
+        const double av = U[(a0 + m) * ld + q0 + kq];
+        const double bv = M[(q0 + kq) * ld + b0 + m];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) L[(a0 + kq + 4 * v) * ld + b0 + m] = acc[v];
+    }
   }
   __syncthreads();
   double* theta = small + SL::THETA;
