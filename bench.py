@@ -105,6 +105,7 @@ def main():
             f"rho=({info['rho_p']:.2e},{info['rho_d']:.2e}) rank path {s.rank_path()}")
     ms_per_step = 1000.0 * sum(times) / len(times)
     last = infos[-1]
+    dbg = s.debug()
     _, lam_f = s.factors()
     rank_x = int(np.sum(lam_f > 1e-8 * max(lam_f.max(), 1e-300))) if lam_f.size else 0
     # roofline of the dominant kernel: the dense pass Z = W B (FP64 MFMA), bytes = 8 n^2 per launch
@@ -156,6 +157,7 @@ def main():
             "obj": last["obj"], "rho_p": last["rho_p"], "rho_d": last["rho_d"],
             "setup_s": round(setup_s, 3), "rank_path": s.rank_path(), "rank_X": rank_x,
             "window": args.window or 50,
+            "rr_calls": int(dbg["rr_calls"]), "rr_cholesky_calls": int(dbg["rr_cholesky_calls"]),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -202,7 +202,10 @@ int proxsdp_rank_path(proxsdp_handle *h, int32_t *iters, int32_t *ranks, int32_t
  * 6 eps_p, 7 eps_d, 8 objective, 9 dual objective, 10 ||X+ - X||_F^2,
  * 13 non-finite code (0 none, 1 Rayleigh-Ritz, 2 full eigensolve, 3 dual
  * step, 4 residuals), 14 dropped basis columns, 15 filter centre, 16 filter
- * half-width, 17 Jacobi sweeps) followed by the Ritz values of the last
+ * half-width, 17 Jacobi sweeps, 18 Newton refinement steps of the last
+ * Rayleigh-Ritz step or -1 if it took the Cholesky path, 19 number of
+ * Rayleigh-Ritz steps on the Cholesky path and 20 of all Rayleigh-Ritz steps
+ * since the last create/reset) followed by the Ritz values of the last
  * Rayleigh-Ritz step in out[64 ..] if count > 64.  Synchronises. */
 int proxsdp_debug_scalars(proxsdp_handle *h, double *out, int32_t count);
 

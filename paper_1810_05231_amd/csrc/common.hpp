@@ -17,6 +17,8 @@
 
 namespace proxsdp {
 
+typedef double d4 __attribute__((ext_vector_type(4)));   // FP64 MFMA accumulator
+
 constexpr int TILE = 64;      // dense write tile and padding unit
 constexpr int KMAX = 64;      // largest subspace width / largest n of the full-eig path
 constexpr int SLICE = 64;     // rows per workgroup in the row-wise kernels
@@ -37,7 +39,8 @@ struct SL {
   static constexpr int PG = TG + kk;
   static constexpr int SC = PG + kk;           // named scalars
   static constexpr int FR = SC + 64;           // reduced factor partials (FAC_RES + KMAX values)
-  static constexpr int TOTAL = FR + 2 * kk + MAX_R1 * KMAX + KMAX;
+  static constexpr int VB = FR + 2 * kk + MAX_R1 * KMAX + KMAX;  // V^T B (KMAX x KMAX) then u_q^T B
+  static constexpr int TOTAL = VB + kk + MAX_R1 * KMAX;
 };
 
 enum Scalar {
@@ -59,6 +62,9 @@ enum Scalar {
   S_FILTC,
   S_FILTE,
   S_SWEEPS,       // Jacobi sweeps of the last small eigensolve
+  S_RRPATH,       // last Rayleigh-Ritz: Newton steps taken (>= 0) or -1 (Cholesky path)
+  S_RRCHOL,       // number of Rayleigh-Ritz calls that took the Cholesky path
+  S_RRCOUNT,      // number of Rayleigh-Ritz calls
   S_COUNT
 };
 
@@ -101,6 +107,7 @@ struct DevProblem {
 // Partial-buffer strides (doubles per slice / per block).
 constexpr int FAC_RES = 2 * KMAX * KMAX + MAX_R1 * KMAX;   // Ritz residual norms^2 (k values)
 constexpr int FAC_STRIDE = FAC_RES + KMAX;
+constexpr int VB_STRIDE = KMAX * KMAX + MAX_R1 * KMAX;  // per-slice partials of V^T B, u^T B
 constexpr int ROW_PART = 4;                 // eps_d^2, <dMX, dy>, dual obj, nonfinite
 constexpr int PAT_PART = 4 + MAX_R1;        // min gersh, ||M*dy||^2 (sparse), obj, unused, cross_q
 

@@ -17,8 +17,6 @@
 
 namespace proxsdp {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
 // Workgroup: 4 waves x 16 columns; rows [j0, j0 + R) of W.
 // MFMA f64 16x16x4 operands (lane l):
 //   A[m][kk]  with m = l % 16, kk = l / 16  := B[j + kk][c0 + m]
@@ -265,6 +263,131 @@ __global__ __launch_bounds__(256) void k_rowwise(const double* __restrict__ B,
   }
 }
 
+// ------------------------------------------------------ implicit operator
+// The iterate W = X - alpha (C - M*(y)) is low rank plus sparse:
+//   W = V diag(lam) V^T + D + sum_q gamma_q u_q u_q^T,
+// with X = V diag(lam) V^T the current factors, D = -alpha C + alpha M*(y) on the
+// sparsity pattern (the values the dense write adds) and gamma_q = alpha sigma_q y_q.
+// Z = W B is applied exactly in FP64 without the dense matrix:
+//   k_vtb           per-slice partials of V^T B (rp x k) and u_q^T B
+//   k_sum_vb        slice sums into small[VB]
+//   k_implicit_apply  Z rows = V_i (lam o V^T B) + sum_{e in row i} D_e B_other(e)
+//                   + sum_q gamma_q u_q[i] (u_q^T B), then the Rayleigh-Ritz Gram
+//                   partials [B^T B, B^T Z, Z^T Z] of the slice.
+__global__ __launch_bounds__(256) void k_vtb(const double* __restrict__ V, int r,
+                                             const double* __restrict__ B, int k, int n_r1,
+                                             const double* __restrict__ r1_u, int npad,
+                                             double* __restrict__ vb_part) {
+  const int s = blockIdx.x;
+  const int i0 = s * SLICE;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
+  const int rb = (r + 15) / 16, kb = k / 16;
+  double* out = vb_part + (int64_t)s * VB_STRIDE;
+  for (int blk = wave; blk < rb * kb; blk += nw) {
+    const int a0 = (blk / kb) * 16, b0 = (blk - (blk / kb) * kb) * 16;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < SLICE; q0 += 4) {
+      const int row = i0 + q0 + kq;
+      const double a = (a0 + m < r) ? V[(int64_t)row * KMAX + a0 + m] : 0.0;
+      const double b = B[(int64_t)row * k + b0 + m];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ra = a0 + kq + 4 * v;
+      if (ra < r) out[ra * KMAX + b0 + m] = acc[v];
+    }
+  }
+  for (int t = threadIdx.x; t < n_r1 * k; t += blockDim.x) {
+    const int q = t / k, c = t - (t / k) * k;
+    double acc = 0.0;
+    for (int i = 0; i < SLICE; ++i) acc += r1_u[(int64_t)q * npad + i0 + i] * B[(int64_t)(i0 + i) * k + c];
+    out[KMAX * KMAX + q * KMAX + c] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_vb(const double* __restrict__ vb_part, int nslices,
+                                                int r, int k, int n_r1, double* __restrict__ small) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n1 = r * k;
+  if (t >= n1 + n_r1 * k) return;
+  const int src = (t < n1) ? (t / k) * KMAX + (t - (t / k) * k)
+                           : KMAX * KMAX + ((t - n1) / k) * KMAX + ((t - n1) - ((t - n1) / k) * k);
+  double acc = 0.0;
+#pragma unroll 8
+  for (int s = 0; s < nslices; ++s) acc += vb_part[(int64_t)s * VB_STRIDE + src];
+  small[SL::VB + src] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_implicit_apply(DevProblem dp, const double* __restrict__ V,
+                                                        int r, const double* __restrict__ small,
+                                                        int lam_off, const double* __restrict__ y,
+                                                        const double* __restrict__ dval,
+                                                        const double* __restrict__ B, int k,
+                                                        double* __restrict__ Z,
+                                                        double* __restrict__ gram_part) {
+  extern __shared__ double sm[];
+  double* sB = sm;                      // SLICE x k
+  double* sZ = sB + SLICE * k;          // SLICE x k
+  double* sM = sZ + SLICE * k;          // r x k   lam o V^T B
+  double* sU = sM + (r > 0 ? r : 1) * k;  // n_r1 x k  gamma o u^T B
+  const int s = blockIdx.x;
+  const int i0 = s * SLICE;
+  const double* lam = small + lam_off;
+  const double alpha = small[SL::SC + S_ALPHA];
+  for (int t = threadIdx.x; t < r * k; t += blockDim.x) {
+    const int a = t / k, c = t - (t / k) * k;
+    sM[t] = lam[a] * small[SL::VB + a * KMAX + c];
+  }
+  for (int t = threadIdx.x; t < dp.n_r1 * k; t += blockDim.x) {
+    const int q = t / k, c = t - (t / k) * k;
+    sU[t] = alpha * dp.r1_sigma[q] * y[dp.r1_row[q]] * small[SL::VB + KMAX * KMAX + q * KMAX + c];
+  }
+  for (int t = threadIdx.x; t < SLICE * k; t += blockDim.x) sB[t] = B[(int64_t)i0 * k + t];
+  __syncthreads();
+  // thread -> (row, column chunk)
+  const int cpt = (k + 3) / 4;                     // columns per thread
+  const int row = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * cpt;
+  const int gi = i0 + row;
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  if (gi < dp.n) {
+    for (int t = 0; t < r; ++t) {
+      const double v = V[(int64_t)gi * KMAX + t];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (u < cpt && c0 + u < k) acc[u] += v * sM[t * k + c0 + u];
+    }
+    for (int q = 0; q < dp.n_r1; ++q) {
+      const double uv = dp.r1_u[(int64_t)q * dp.npad + gi];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (u < cpt && c0 + u < k) acc[u] += uv * sU[q * k + c0 + u];
+    }
+    for (int e0 = dp.sym_ptr[gi]; e0 < dp.sym_ptr[gi + 1]; ++e0) {
+      const int e = dp.sym_e[e0];
+      const int ea = dp.pat_a[e], eb = dp.pat_b[e];
+      const int other = (ea == gi) ? eb : ea;
+      const double dv = dval[e];
+      const double* brow = B + (int64_t)other * k + c0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (u < cpt && c0 + u < k) acc[u] += dv * brow[u];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    if (u < cpt && c0 + u < k) {
+      sZ[row * k + c0 + u] = acc[u];
+      Z[(int64_t)gi * k + c0 + u] = acc[u];
+    }
+  }
+  __syncthreads();
+  gram_blocks_mfma(sB, sZ, k, gram_part + (int64_t)s * 3 * k * k);
+}
+
 // Fills rows < n of an npad x ldk block (columns [c0, c1)) with uniform(-1, 1)
 // values from a counter-based hash (splitmix64 finaliser) of (seed, row, col);
 // rows >= n get 0.  Columns < c0 are copied from `src` when src != null.
@@ -348,31 +471,15 @@ __global__ __launch_bounds__(256) void k_write_w(double* __restrict__ W, int64_t
   const int a0 = I * TILE, b0 = J * TILE;
   const int nq = rank1 ? dp.n_r1 : 0;
   const int rr = r + nq;
-  const int rrp = (rr + 3) & ~3;          // contraction length, multiple of 4
-  const int lds = rrp + 1;                // odd stride against bank conflicts
-  double* sT = sm;                        // 64 x 65
-  double* sVa = sT + TILE * (TILE + 1);   // 64 x lds:  V rows of the tile's row block
-  double* sVb = sVa + TILE * lds;         // 64 x lds:  lam-scaled V rows of the column block
+  double* sT = sm;                        // 64 x 65 output tile
   const double* lam = small + lam_off;
   const double alpha = small[SL::SC + S_ALPHA];
-  for (int t = threadIdx.x; t < TILE * rrp; t += blockDim.x) {
-    const int i = t / rrp, q = t - (t / rrp) * rrp;
-    double va = 0.0, vb = 0.0;
-    if (q < r) {
-      if (a0 + i < n) va = V[(int64_t)(a0 + i) * ldv + q];
-      if (b0 + i < n) vb = V[(int64_t)(b0 + i) * ldv + q] * lam[q];
-    } else if (q < rr) {
-      const int u = q - r;
-      const double gamma = alpha * dp.r1_sigma[u] * y[dp.r1_row[u]];
-      va = dp.r1_u[(int64_t)u * dp.npad + a0 + i];
-      vb = dp.r1_u[(int64_t)u * dp.npad + b0 + i] * gamma;
-    }
-    sVa[i * lds + q] = va;
-    sVb[i * lds + q] = vb;
-  }
-  __syncthreads();
-  // low-rank part on MFMA f64 16x16x4: wave w owns rows [16w, 16w + 16) of the tile,
-  //   A[m][kk] = Va[16w + m][t0 + kk],  B[kk][n] = lam Vb[16 nb + n][t0 + kk]
+  // low-rank part on MFMA f64 16x16x4: wave w owns rows [16w, 16w + 16) of the
+  // tile; operands straight from the factors (L2 resident), 16 contraction
+  // indices per batch with all loads issued before the MFMAs:
+  //   A[m][q] = Vrow(a0 + 16w + m)[q],  B[q][c] = s_q Vrow(b0 + 16nb + c)[q]
+  // with s_q = lambda_q for factor columns and alpha sigma_u y_u for the
+  // rank-one terms u = q - r.
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   {
@@ -380,13 +487,35 @@ __global__ __launch_bounds__(256) void k_write_w(double* __restrict__ W, int64_t
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[nb] = d4{0.0, 0.0, 0.0, 0.0};
     const int m = lane & 15, kq = lane >> 4;
-    for (int t0 = 0; t0 < rrp; t0 += 4) {
-      const double a = sVa[(16 * w + m) * lds + t0 + kq];
+    const int arow = a0 + 16 * w + m;
+    for (int t0 = 0; t0 < rr; t0 += 16) {
+      double av[4], bv[4][4];
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const double b = sVb[(16 * nb + m) * lds + t0 + kq];
-        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[nb], 0, 0, 0);
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int q = t0 + 4 * s4 + kq;
+        if (q < r) {
+          const double sc = lam[q];
+          av[s4] = V[(int64_t)arow * ldv + q];
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) bv[s4][nb] = V[(int64_t)(b0 + 16 * nb + m) * ldv + q] * sc;
+        } else if (q < rr) {
+          const int u = q - r;
+          const double sc = alpha * dp.r1_sigma[u] * y[dp.r1_row[u]];
+          const double* uu = dp.r1_u + (int64_t)u * dp.npad;
+          av[s4] = uu[arow];
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) bv[s4][nb] = uu[b0 + 16 * nb + m] * sc;
+        } else {
+          av[s4] = 0.0;
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) bv[s4][nb] = 0.0;
+        }
       }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+          acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bv[s4][nb], acc[nb], 0, 0, 0);
     }
     // result lane l, register v: row l/16 + 4 v, column l % 16
 #pragma unroll

@@ -649,15 +649,15 @@ static void launch_reduce(const double* part, int nchunks, double* Z, const doub
 #endif
 
 // jac_tol: relative off-diagonal level at which the Jacobi sweeps stop.
+// oa_steps: largest number of Newton refinement steps before the Cholesky path.
 static void launch_rr(const double* gram_part, int nsl, double* small, int k, int r, int lam_off,
-                      int filter, double jac_tol, hipStream_t st) {
+                      int filter, double jac_tol, hipStream_t st, int oa_steps = 5) {
   const int kk = k * k;
   hipLaunchKernelGGL(k_sum_grams, dim3((3 * kk + 255) / 256), dim3(256), 0, st, gram_part, nsl, k,
                      small);
-  const size_t lds = (3 * (size_t)k * (k + 1) + 3 * KMAX + 3 * (KMAX / 2 + 1)) * sizeof(double) +
-                     (KMAX + 4) * sizeof(int);
+  const size_t lds = small_rr_lds_doubles(k) * sizeof(double) + (2 * KMAX + 4) * sizeof(int);
   hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(PROXSDP_RR_THREADS), lds, st, small, k, r, lam_off,
-                     filter, jac_tol);
+                     filter, jac_tol, oa_steps);
 }
 
 static void launch_rowwise(proxsdp_handle* H, const double* B, double* V, int r, const double* Vold,
@@ -680,9 +680,7 @@ static void launch_full(proxsdp_handle* H, double* V, int r, const double* Vold,
 static void launch_write(proxsdp_handle* H, double* Wout, int64_t ld, const double* V, int r,
                          int lam_off, bool sparse, bool rank1, const FinArgs* fin) {
   const int ts = H->npad / TILE;
-  const int rr = r + (rank1 ? H->dp.n_r1 : 0);
-  const int rrp = (rr + 3) & ~3;
-  const size_t lds = ((size_t)TILE * (TILE + 1) + 2 * (size_t)TILE * (rrp + 1)) * sizeof(double);
+  const size_t lds = (size_t)TILE * (TILE + 1) * sizeof(double);
   FinArgs f{};
   if (fin) f = *fin;
   hipLaunchKernelGGL(k_write_w, dim3(ts * (ts + 1) / 2 + (fin ? 1 : 0)), dim3(256), lds, H->st, Wout, ld,
@@ -871,6 +869,24 @@ static int fill_info(proxsdp_handle* H, const IterRecord& rec, double nonfinite)
   return PROXSDP_OK;
 }
 
+// lambda_r of the current W from one dense pass and a Rayleigh-Ritz step on
+// the Cholesky path (every Ritz value resolved).  The Newton path of the
+// small eigensolver leaves the non-positive unwanted tail unresolved, so the
+// rank test confirms a passing lambda_r this way before the solve stops.
+// Overwrites only data the next iteration recomputes.
+static int confirm_lambda_r(proxsdp_handle* H, double* lam_r) {
+  hipStream_t st = H->st;
+  const double* Bc = H->B[H->bcur];
+  launch_block(H->W, H->npad, H->n, H->npad, Bc, H->k, H->part, H->ch, true, st);
+  launch_reduce(H->part, H->ch.nchunks, H->Z, Bc, nullptr, H->npad, H->k, H->gram_part, 0, 0.0, 1.0,
+                true, st);
+  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(H->iters & 1), 1, 1e-15, st, 0);
+  HIP_OK(hipMemcpyAsync(lam_r, H->small + SL::SC + S_LAMR, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  H->passes += 1;
+  return PROXSDP_OK;
+}
+
 // Control check after iteration H->iters (a multiple of check_every).
 static int control(proxsdp_handle* H) {
   const int ce = H->opt.check_every;
@@ -890,7 +906,14 @@ static int control(proxsdp_handle* H) {
     H->status = PROXSDP_STATUS_NUMERICAL;
   } else if (std::max(rho_p, rho_d) <= H->opt.tol) {
     const int n = H->n;
-    if (H->r >= n || (double)(n - H->r) * std::max(rec.lambda_r, 0.0) <= H->eps_lambda) {
+    bool pass = H->r >= n || (double)(n - H->r) * std::max(rec.lambda_r, 0.0) <= H->eps_lambda;
+    if (pass && H->r < n && !H->full) {
+      double lr = rec.lambda_r;
+      const int rc = confirm_lambda_r(H, &lr);
+      if (rc) return rc;
+      pass = (double)(n - H->r) * std::max(lr, 0.0) <= H->eps_lambda;
+    }
+    if (pass) {
       H->status = PROXSDP_STATUS_CONVERGED;
     } else if (H->r >= H->r_cap) {
       H->hist.push_back(comb);
@@ -1288,7 +1311,8 @@ int proxsdp_project_psd(const void* S, int32_t n, int64_t lds, int32_t r, int32_
       launch_block(Sd, lds, n, H.npad, Bc, k, H.part, H.ch, false, st);
       launch_reduce(H.part, H.ch.nchunks, H.Z, Bc, nullptr, H.npad, k, H.gram_part, 0, 0.0, 1.0, true, st);
       const int n_unshifted = 6;
-      launch_rr(H.gram_part, H.nsl, H.small, k, re, lam_off, rd >= n_unshifted ? 1 : 0, 1e-15, st);
+      launch_rr(H.gram_part, H.nsl, H.small, k, re, lam_off, rd >= n_unshifted ? 1 : 0, 1e-15, st,
+                0);
       if (rd == n_unshifted - 1) hipLaunchKernelGGL(k_set_lower_bound, dim3(1), dim3(64), 0, st, H.small);
       launch_rowwise(&H, Bc, H.V[0], re, H.V[0], 0, Bn, st);
       const bool check = (rd % 4 == 3) || rd == max_rounds - 1;

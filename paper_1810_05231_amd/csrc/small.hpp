@@ -14,7 +14,7 @@ namespace proxsdp {
 
 // Index of the partner pairs in round `rnd` of a kk-player round robin
 // (kk even): player 0 stays, the others rotate.
-__device__ inline int rr_player(int pos, int rnd, int kk) {
+__device__ __forceinline__ int rr_player(int pos, int rnd, int kk) {
   if (pos == 0) return 0;
   return ((pos - 1 + rnd) % (kk - 1)) + 1;
 }
@@ -27,12 +27,19 @@ __device__ inline int rr_player(int pos, int rnd, int kk) {
 // off-diagonal norm is below 1e-15 of the diagonal norm.
 // `cs` is LDS scratch of 3 (KMAX/2 + 1) doubles; `red` of 2 doubles.
 // Returns the number of sweeps.
-__device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double* cs, int* flag,
-                          int max_sweeps, double tol_off = 1e-15) {
+//
+// `threshold` (for nearly diagonal input): a pair is rotated only if its
+// off-diagonal entry exceeds tol_off ||diag||_2 / k, and a round with no such
+// pair skips its update (one barrier instead of two).
+// `imp` (optional, threshold mode): only pairs with imp[p] or imp[q] set are
+// rotated and counted in the off-diagonal test.
+__device__ __forceinline__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double* cs, int* flag,
+                          int max_sweeps, double tol_off = 1e-15, bool threshold = false,
+                          const int* imp = nullptr) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int t = tid; t < k * k; t += nt) {
-    const int i = t / k, j = t - (t / k) * k;
-    U[i * ldu + j] = (i == j) ? 1.0 : 0.0;
+  for (int t = tid; t < (k << 6); t += nt) {
+    const int i = t >> 6, j = t & 63;
+    if (j < k) U[i * ldu + j] = (i == j) ? 1.0 : 0.0;
   }
   const int kk = (k & 1) ? k + 1 : k;
   const int np = kk / 2;
@@ -42,15 +49,19 @@ __device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double*
   int* qq = pp + np;
   int sweeps = 0;
   __shared__ double offd[2];
+  __shared__ int anyrot[2];
+  if (tid == 0) { anyrot[0] = 1; anyrot[1] = 1; }
   for (int sw = 0; sw < max_sweeps; ++sw) {
     // convergence test on the off-diagonal mass
     if (tid == 0) { offd[0] = 0.0; offd[1] = 0.0; *flag = 0; }
     __syncthreads();
     double off = 0.0, dg = 0.0;
-    for (int t = tid; t < k * k; t += nt) {
-      const int i = t / k, j = t - (t / k) * k;
+    for (int t = tid; t < (k << 6); t += nt) {
+      const int i = t >> 6, j = t & 63;
+      if (j >= k) continue;
       const double v = A[i * lda + j];
-      if (i == j) dg += v * v; else off += v * v;
+      if (i == j) dg += v * v;
+      else if (!imp || imp[i] || imp[j]) off += v * v;
     }
     for (int o = 32; o > 0; o >>= 1) {
       off += __shfl_xor(off, o);
@@ -62,24 +73,28 @@ __device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double*
     }
     __syncthreads();
     if (!(offd[0] > tol_off * tol_off * offd[1]) || !(offd[0] > 1e-300)) break;
+    const double pair_thr = threshold ? tol_off * sqrt(offd[1]) / k : 0.0;
     for (int rnd = 0; rnd < kk - 1; ++rnd) {
+      if (threshold && tid == 0) anyrot[(rnd + 1) & 1] = 0;
       for (int i = tid; i < np; i += nt) {
         int p = rr_player(i, rnd, kk), q = rr_player(kk - 1 - i, rnd, kk);
         if (p > q) { const int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
-        if (q < k) {
+        if (q < k && (!imp || imp[p] || imp[q])) {
           const double app = A[p * lda + p], aqq = A[q * lda + q], apq = A[p * lda + q];
-          const double thr = 1e-18 * sqrt(fabs(app * aqq)) + 1e-300;
+          const double thr = fmax(1e-18 * sqrt(fabs(app * aqq)), pair_thr) + 1e-300;
           if (fabs(apq) > thr) {
             const double th = (aqq - app) / (2.0 * apq);
             const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
             s = t * c;
+            if (threshold) anyrot[rnd & 1] = 1;
           }
         }
         cc[i] = c; ss[i] = s; pp[i] = p; qq[i] = (q < k) ? q : -1;
       }
       __syncthreads();
+      if (threshold && anyrot[rnd & 1] == 0) continue;
       // A <- J^T A J blockwise; U <- U J.  A thread keeps one row pair (its
       // rotation in registers) and handles column pairs / rows in batches of
       // four: all loads, then the arithmetic, then all stores, so the LDS
@@ -152,7 +167,7 @@ __device__ int jacobi_eig(double* A, int lda, double* U, int ldu, int k, double*
 // Sorts eigenvalues (diagonal of A) decreasingly: writes values to `vals`
 // and the permutation to `perm`.  Rank sort: thread i counts the entries that
 // precede it (larger, or equal with a smaller index), k <= KMAX.
-__device__ void sort_desc(const double* A, int lda, int k, double* vals, int* perm) {
+__device__ __forceinline__ void sort_desc(const double* A, int lda, int k, double* vals, int* perm) {
   // identity first, so that a non-finite value (flagged elsewhere) can only
   // leave a valid index behind
   for (int i = threadIdx.x; i < k; i += blockDim.x) {
@@ -175,9 +190,147 @@ __device__ void sort_desc(const double* A, int lda, int k, double* vals, int* pe
   __syncthreads();
 }
 
+// One 16 x 16 tile of op(A) B on FP64 MFMA 16x16x4, KQ = k / 4.  All operand
+// loads are issued before the MFMA chain.  Result element v of a lane is row
+// a0 + 4 (lane / 16) + ... see the callers: row a0 + kq + 4 v, column b0 + m.
+template <int KQ>
+__device__ __forceinline__ d4 tile_mm(const double* A, int lda, bool ta, const double* B, int ldb,
+                                      int a0, int b0, int m, int kq) {
+  double av[KQ], bv[KQ];
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    av[q] = ta ? A[(4 * q + kq) * lda + a0 + m] : A[(a0 + m) * lda + 4 * q + kq];
+    bv[q] = B[(4 * q + kq) * ldb + b0 + m];
+  }
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+  return acc;
+}
+
+template <int KQ>
+__device__ __forceinline__ void lds_mm_k(double* C, int ldc, const double* A, int lda, bool ta,
+                                         const double* B, int ldb, bool sym) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
+  constexpr int kb = KQ / 4;
+  constexpr int ntiles = kb * kb;
+  for (int blk = wave; blk < ntiles; blk += nw) {
+    const int ta_ = blk / kb, tb_ = blk - (blk / kb) * kb;
+    if (sym && ta_ > tb_) continue;
+    const int a0 = ta_ * 16, b0 = tb_ * 16;
+    const d4 acc = tile_mm<KQ>(A, lda, ta, B, ldb, a0, b0, m, kq);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      C[(a0 + kq + 4 * v) * ldc + b0 + m] = acc[v];
+      if (sym && ta_ != tb_) C[(b0 + m) * ldc + a0 + kq + 4 * v] = acc[v];
+    }
+  }
+}
+
+// C = op(A) B for k x k matrices in LDS (k in {16, 32, 48, 64}) on FP64 MFMA,
+// op(A) = A^T when `ta`; `sym`: the product is known to be symmetric, only
+// the upper tiles are computed and mirrored.  Output tiles are spread over
+// the waves.  C must not alias A or B; the caller synchronises afterwards.
+__device__ __forceinline__ void lds_mm(double* C, int ldc, const double* A, int lda, bool ta,
+                                       const double* B, int ldb, int k, bool sym = false) {
+  switch (k) {
+    case 16: lds_mm_k<4>(C, ldc, A, lda, ta, B, ldb, sym); break;
+    case 32: lds_mm_k<8>(C, ldc, A, lda, ta, B, ldb, sym); break;
+    case 48: lds_mm_k<12>(C, ldc, A, lda, ta, B, ldb, sym); break;
+    default: lds_mm_k<16>(C, ldc, A, lda, ta, B, ldb, sym); break;
+  }
+}
+
+// Out = D X F[:, perm] (perm == nullptr: identity; d == nullptr: D = I) with X
+// k x k in global memory (row stride ldx) and F in LDS.  A wave owns whole
+// 16-row strips and loads its strip of X before any store, so Out may be X
+// itself.
+__device__ __forceinline__ void strip_mm(double* Out, int ldo, const double* X, int ldx,
+                                         const double* F, int ldf, const int* perm,
+                                         const double* d, int k) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int m = lane & 15, kq = lane >> 4, kb = k / 16, ks = k / 4;
+  for (int a0 = wave * 16; a0 < k; a0 += nw * 16) {
+    double xa[KMAX / 4];
+#pragma unroll
+    for (int q = 0; q < KMAX / 4; ++q) xa[q] = (q < ks) ? X[(a0 + m) * ldx + 4 * q + kq] : 0.0;
+    d4 acc[KMAX / 16];
+#pragma unroll
+    for (int b = 0; b < KMAX / 16; ++b) {
+      acc[b] = d4{0.0, 0.0, 0.0, 0.0};
+      if (b < kb) {
+        const int col = perm ? perm[b * 16 + m] : b * 16 + m;
+        double fv[KMAX / 4];
+#pragma unroll
+        for (int q = 0; q < KMAX / 4; ++q) fv[q] = (q < ks) ? F[(4 * q + kq) * ldf + col] : 0.0;
+#pragma unroll
+        for (int q = 0; q < KMAX / 4; ++q)
+          if (q < ks) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[q], fv[q], acc[b], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < KMAX / 16; ++b) {
+      if (b < kb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = a0 + kq + 4 * v;
+          Out[row * ldo + b * 16 + m] = (d ? d[row] : 1.0) * acc[b][v];
+        }
+      }
+    }
+  }
+}
+
+// Deterministic workgroup reduction of (sum a, sum b, max(c, 0)); every thread
+// gets the result.  `red` is LDS scratch of 3 * (blockDim / 64) doubles.
+__device__ __forceinline__ void block_sum2_max1(double& a, double& b, double& c, double* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+    c = fmax(c, __shfl_xor(c, o));
+  }
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[3 * wave] = a;
+    red[3 * wave + 1] = b;
+    red[3 * wave + 2] = c;
+  }
+  __syncthreads();
+  a = 0.0; b = 0.0; c = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    a += red[3 * w];
+    b += red[3 * w + 1];
+    c = fmax(c, red[3 * w + 2]);
+  }
+}
+
 // Rayleigh-Ritz on span(B) from the reduced Grams G = B^T B, T = B^T W B,
-// P = (W B)^T (W B).  Generalised problem T s = theta G s through a Cholesky
-// factor of the column-equilibrated G (one CholeskyQR step folded into RR).
+// P = (W B)^T (W B): the pencil T s = theta G s.
+//
+// Newton path (nearly converged basis, the usual case with warm starts): the
+// basis coefficients X (start: the column equilibration D) are refined by the
+// quadratically convergent update of Ogita and Aishima (2018), generalised to
+// the G inner product: with R = I - X^T G X, S = X^T T X and
+// mu_i = S_ii / (1 - R_ii),
+//   E_ij = (S_ij + mu_j R_ij) / (mu_j - mu_i)   (separated pairs),
+//   E_ij = R_ij / 2                             (otherwise and on i = j),
+//   X <- X (I + E),
+// with matrix products only (MFMA).  The update is applied to the pairs that
+// touch an important index (a positive value among the r largest) whose gap
+// exceeds delta = 2 (||off(S)|| + max|mu| ||R||) and whose coupling is weak
+// (|E_ij| <= 0.1); the unwanted tail is only re-orthonormalised (its dense
+// near-degenerate spectrum makes Newton steps there erratic).  The result is
+// accepted if X^T G X is within 1e-12 of I, the important couplings are below
+// 1e-4 max|mu| and a Gershgorin bound of the tail block shows that no tail
+// eigenvalue exceeds max(mu_(r), 0); threshold Jacobi on the important pairs
+// finishes.  Otherwise the Cholesky path is taken.
+//
+// Cholesky path: generalised problem through a Cholesky factor of the
+// column-equilibrated G (one CholeskyQR step folded into RR), cyclic Jacobi on
+// L^{-1} T L^{-T}, back substitution.
+//
 // Writes (small): S (k x k, V = B S with V^T V = I), THETA (decreasing), RES
 // (relative Ritz residuals ||W v - theta v|| / max|theta|), lambda_+ of the r
 // kept pairs at lam_off, S_LAMR/S_LAMR1/S_MAXRES/S_NORMW, and the next-basis
@@ -185,10 +338,12 @@ __device__ void sort_desc(const double* A, int lda, int k, double* vals, int* pe
 //   Bn_i = (W - c I) v_i / ||(W - c I) v_i||,  c = (lo + theta_k) / 2,
 // where lo = small[S_GERSH] bounds the spectrum from below (filter != 0;
 // filter == 0 gives Bn_i = W v_i / ||W v_i||).
-// LDS: 3 k x k matrices (L, Tt, U) + vectors.
+// k is a multiple of 16 (<= KMAX).  Loops over k x k entries use the index
+// map t -> (t >> 6, t & 63) (no integer division).  LDS: 4 k x (k + 1)
+// matrices + vectors.
 // Dot product of length n over LDS with four independent accumulators
 // (keeps several LDS loads in flight).
-__device__ inline double lds_dot(const double* a, int sa, const double* b, int sb, int n) {
+__device__ __forceinline__ double lds_dot(const double* a, int sa, const double* b, int sb, int n) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int j = 0;
   for (; j + 3 < n; j += 4) {
@@ -201,160 +356,251 @@ __device__ inline double lds_dot(const double* a, int sa, const double* b, int s
   return (s0 + s1) + (s2 + s3);
 }
 
+// LDS doubles of k_small_rr for subspace width k.
+__host__ __device__ inline size_t small_rr_lds_doubles(int k) {
+  return 4 * (size_t)k * (k + 1) + 4 * KMAX + 3 * (KMAX / 2 + 1) + 16;
+}
+
+#define RR_FOR_KK(t, i, j)                              \
+  for (int t = tid; t < (k << 6); t += nt)              \
+    if (const int j = t & 63, i = t >> 6; j < k)
+
 __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, int k, int r,
-                                                  int lam_off, int filter, double jac_tol) {
+                                                  int lam_off, int filter, double jac_tol,
+                                                  int oa_steps) {
   extern __shared__ double sm[];
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int kk = k * k;
   const int ld = k + 1;           // odd LDS row stride: column walks hit distinct banks
-  double* L = sm;                 // k x ld
-  double* M = L + k * ld;         // k x ld
-  double* U = M + k * ld;         // k x ld
-  double* d = U + k * ld;         // KMAX
+  double* B0 = sm;                // four k x ld matrices
+  double* B1 = B0 + k * ld;
+  double* B2 = B1 + k * ld;
+  double* B3 = B2 + k * ld;
+  double* d = B3 + k * ld;        // KMAX
   double* vals = d + KMAX;        // KMAX
   double* inv = vals + KMAX;      // KMAX
-  double* cs = inv + KMAX;        // 3 * (KMAX/2 + 1)
-  int* perm = reinterpret_cast<int*>(cs + 3 * (KMAX / 2 + 1));
+  double* mu = inv + KMAX;        // KMAX
+  double* cs = mu + KMAX;         // 3 * (KMAX/2 + 1)
+  double* red = cs + 3 * (KMAX / 2 + 1);   // 16
+  int* perm = reinterpret_cast<int*>(red + 16);
   int* flag = perm + KMAX;  // [0] dropped count, [1] jacobi
+  int* imp = flag + 4;      // KMAX: pair importance on the Newton path
   const double* G = small + SL::GG;
   const double* T = small + SL::TG;
   const double* P = small + SL::PG;
-  // 1. equilibrate: d_i = 1/sqrt(G_ii); L = D G D (+ shift), M = D T D (symmetrised)
+  double* Sg = small + SL::S;     // coefficients (global, row stride KMAX)
+  // 1. equilibrate: d_i = 1/sqrt(G_ii)
   for (int t = tid; t < k; t += nt) {
     const double g = G[t * k + t];
     d[t] = (g > 0.0) ? 1.0 / sqrt(g) : 1.0;
   }
   if (tid == 0) { flag[0] = 0; flag[1] = 0; }
   __syncthreads();
-  for (int t = tid; t < kk; t += nt) {
-    const int i = t / k, j = t - (t / k) * k;
-    const double tij = 0.5 * (T[i * k + j] + T[j * k + i]);
-    const double gij = 0.5 * (G[i * k + j] + G[j * k + i]);
-    L[i * ld + j] = gij * d[i] * d[j] + ((i == j) ? 1e-15 * k : 0.0);
-    M[i * ld + j] = tij * d[i] * d[j];
-  }
-  __syncthreads();
-  // 2. Cholesky of the equilibrated G (lower, in L).  A column whose pivot
-  //    falls below 1e-14 (numerically dependent on the previous ones) is
-  //    dropped: L_jj = 1 with a zero sub-column, so its orthogonalised
-  //    direction is the tiny remainder and its Ritz value is ~0.
-  for (int j = 0; j < k; ++j) {
-    const double piv = L[j * ld + j];
-    const bool dropped = !(piv > 1e-14);
-    const double ljj = dropped ? 1.0 : sqrt(piv);
-    for (int i = j + 1 + tid; i < k; i += nt) L[i * ld + j] = dropped ? 0.0 : L[i * ld + j] / ljj;
-    __syncthreads();
-    if (tid == 0) {
-      L[j * ld + j] = ljj;
-      if (dropped) flag[0] += 1;
-    }
-    // trailing update of the lower triangle (i >= c > j), four entries per batch
-    const int rem = k - 1 - j;
-    for (int t0 = tid; t0 < rem * rem; t0 += 4 * nt) {
-      double lij[4], lcj[4], lic[4];
-      int pos[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int t = t0 + u * nt;
-        const int i = j + 1 + t / rem, c = j + 1 + (t - (t / rem) * rem);
-        const bool on = t < rem * rem && c <= i;
-        pos[u] = on ? i * ld + c : -1;
-        lij[u] = on ? L[i * ld + j] : 0.0;
-        lcj[u] = on ? L[c * ld + j] : 0.0;
-        lic[u] = on ? L[i * ld + c] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (pos[u] >= 0) L[pos[u]] = lic[u] - lij[u] * lcj[u];
+  int sweeps = 0, path = -1;
+  double* Sbuf;   // sorted Ritz coefficients (k x ld)
+  double* Pbuf;   // P (k x ld)
+  double* Ybuf;   // P S (k x ld)
+  // ---------------------------------------------------------- Newton path
+  bool newton_ok = false;
+  if (oa_steps > 0) {
+    double* Gc = B0;
+    double* Sc = B1;
+    double* F = B2;
+    double* Tm = B3;
+    RR_FOR_KK(t, i, j) {
+      Gc[i * ld + j] = 0.5 * (G[i * k + j] + G[j * k + i]) * d[i] * d[j];
+      Sc[i * ld + j] = 0.5 * (T[i * k + j] + T[j * k + i]) * d[i] * d[j];
+      Sg[i * KMAX + j] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
+    double offR = 1.0, offS = 1.0, smax = 1.0;
+    int st = 0;
+    for (;; ++st) {
+      for (int t = tid; t < k; t += nt) mu[t] = Sc[t * ld + t] / Gc[t * ld + t];
+      __syncthreads();
+      // important pairs: those touching a positive value among the r largest
+      for (int t = tid; t < k; t += nt) {
+        const double v = mu[t];
+        int rank = 0;
+        for (int j = 0; j < k; ++j) rank += (mu[j] > v) || (mu[j] == v && j < t);
+        imp[t] = (rank < r && v > 0.0) ? 1 : 0;
+        if (rank == (r < k ? r : k) - 1) red[15] = v;   // r-th largest
+      }
+      __syncthreads();
+      double aR = 0.0, aS = 0.0, mx = 0.0;
+      RR_FOR_KK(t, i, j) {
+        const double rij = ((i == j) ? 1.0 : 0.0) - Gc[i * ld + j];
+        aR += rij * rij;
+        if (i == j) mx = fmax(mx, fabs(mu[i]));
+        else if (imp[i] || imp[j]) aS += Sc[i * ld + j] * Sc[i * ld + j];
+      }
+      block_sum2_max1(aR, aS, mx, red);
+      offR = sqrt(aR);
+      offS = sqrt(aS);
+      smax = fmax(mx, 1e-300);
+      const bool conv = offR <= 1e-13 && offS <= fmax(jac_tol, 1e-15) * smax;
+      if (conv || st == oa_steps || !(offR < 0.5) || !isfinite(offS) || !isfinite(smax)) break;
+      const double delta = 2.0 * (offS + smax * offR);
+      RR_FOR_KK(t, i, j) {
+        const double rij = ((i == j) ? 1.0 : 0.0) - Gc[i * ld + j];
+        double e = 0.5 * rij;
+        const double gap = mu[j] - mu[i];
+        const double num = Sc[i * ld + j] + mu[j] * rij;
+        if (i != j && (imp[i] || imp[j]) && fabs(gap) > delta && fabs(num) <= 0.1 * fabs(gap))
+          e = num / gap;
+        F[i * ld + j] = ((i == j) ? 1.0 : 0.0) + e;
+      }
+      __syncthreads();
+      lds_mm(Tm, ld, Gc, ld, false, F, ld, k);
+      __syncthreads();
+      lds_mm(Gc, ld, F, ld, true, Tm, ld, k, true);
+      __syncthreads();
+      lds_mm(Tm, ld, Sc, ld, false, F, ld, k);
+      __syncthreads();
+      lds_mm(Sc, ld, F, ld, true, Tm, ld, k, true);
+      strip_mm(Sg, KMAX, Sg, KMAX, F, ld, nullptr, nullptr, k);
+      __syncthreads();
+    }
+    newton_ok = offR <= 1e-12 && offS <= 1e-4 * smax;
+    if (newton_ok) {
+      // The unwanted tail is not diagonalised, so its block may hide an
+      // eigenvalue above the kept ones.  Gershgorin bound of that block:
+      // accept only if no tail eigenvalue can exceed max(mu_(r), 0).
+      double z0 = 0.0, z1 = 0.0, gb = 0.0;
+      for (int i = tid; i < k; i += nt) {
+        if (imp[i]) continue;
+        double rad = 0.0;
+        for (int j = 0; j < k; ++j)
+          if (j != i && !imp[j]) rad += fabs(Sc[i * ld + j]);
+        gb = fmax(gb, mu[i] + rad);
+      }
+      const double thr = fmax(red[15], 0.0);
+      block_sum2_max1(z0, z1, gb, red);   // max(gb, 0) over the tail rows
+      newton_ok = gb <= thr;
+    }
+    if (newton_ok) path = st;
   }
-  // 3. Tt = L^{-1} M L^{-T}: U = L^{-1} M column by column, then M = L^{-1} U^T.
-  //    Four lanes per column share each dot product (shuffle reduction).
-  {
-    const int c = tid >> 2, part = tid & 3;
-    if (c < k) {
-      for (int i = 0; i < k; ++i) {
-        double sacc = 0.0;
-        for (int j = part; j < i; j += 4) sacc += L[i * ld + j] * U[j * ld + c];
-        sacc += __shfl_xor(sacc, 1);
-        sacc += __shfl_xor(sacc, 2);
-        const double v = (M[i * ld + c] - sacc) / L[i * ld + i];
-        if (part == 0) U[i * ld + c] = v;
+  // -------------------------------------------------------- Cholesky path
+  if (!newton_ok) {
+    double* L = B0;
+    double* M = B1;
+    double* U = B2;
+    RR_FOR_KK(t, i, j) {
+      const double tij = 0.5 * (T[i * k + j] + T[j * k + i]);
+      const double gij = 0.5 * (G[i * k + j] + G[j * k + i]);
+      L[i * ld + j] = gij * d[i] * d[j] + ((i == j) ? 1e-15 * k : 0.0);
+      M[i * ld + j] = tij * d[i] * d[j];
+    }
+    __syncthreads();
+    // Cholesky of the equilibrated G (lower, in L).  A column whose pivot
+    // falls below 1e-14 (numerically dependent on the previous ones) is
+    // dropped: L_jj = 1 with a zero sub-column, so its orthogonalised
+    // direction is the tiny remainder and its Ritz value is ~0.
+    {
+      const int c = tid & 63, ty = tid >> 6, nty = nt >> 6;
+      for (int j = 0; j < k; ++j) {
+        const double piv = L[j * ld + j];
+        const bool dropped = !(piv > 1e-14);
+        const double ljj = dropped ? 1.0 : sqrt(piv);
+        const double rl = 1.0 / ljj;
+        for (int i = j + 1 + tid; i < k; i += nt) L[i * ld + j] = dropped ? 0.0 : L[i * ld + j] * rl;
+        __syncthreads();
+        if (tid == 0) {
+          L[j * ld + j] = ljj;
+          if (dropped) flag[0] += 1;
+        }
+        // trailing update of the lower triangle: lane c owns column c, the
+        // waves split the rows i >= c
+        if (c > j && c < k) {
+          const double lcj = L[c * ld + j];
+          for (int i = c + ty; i < k; i += nty) L[i * ld + c] -= L[i * ld + j] * lcj;
+        }
+        __syncthreads();
+      }
+    }
+    // Tt = L^{-1} M L^{-T}: U = L^{-1} M column by column, then M = L^{-1} U^T.
+    // Four lanes per column share each dot product (shuffle reduction).
+    {
+      const int c = tid >> 2, part = tid & 3;
+      if (c < k) {
+        for (int i = 0; i < k; ++i) {
+          double sacc = 0.0;
+          for (int j = part; j < i; j += 4) sacc += L[i * ld + j] * U[j * ld + c];
+          sacc += __shfl_xor(sacc, 1);
+          sacc += __shfl_xor(sacc, 2);
+          const double v = (M[i * ld + c] - sacc) / L[i * ld + i];
+          if (part == 0) U[i * ld + c] = v;
+        }
+      }
+      __syncthreads();
+      if (c < k) {
+        for (int i = 0; i < k; ++i) {
+          double sacc = 0.0;
+          for (int j = part; j < i; j += 4) sacc += L[i * ld + j] * M[j * ld + c];
+          sacc += __shfl_xor(sacc, 1);
+          sacc += __shfl_xor(sacc, 2);
+          const double v = (U[c * ld + i] - sacc) / L[i * ld + i];
+          if (part == 0) M[i * ld + c] = v;
+        }
       }
     }
     __syncthreads();
-    if (c < k) {
-      for (int i = 0; i < k; ++i) {
-        double sacc = 0.0;
-        for (int j = part; j < i; j += 4) sacc += L[i * ld + j] * M[j * ld + c];
-        sacc += __shfl_xor(sacc, 1);
-        sacc += __shfl_xor(sacc, 2);
-        const double v = (U[c * ld + i] - sacc) / L[i * ld + i];
-        if (part == 0) M[i * ld + c] = v;
-      }
-    }
   }
-  __syncthreads();
-  for (int t = tid; t < kk; t += nt) {
-    const int i = t / k, j = t - (t / k) * k;
+  // symmetrise the projected matrix (B1)
+  RR_FOR_KK(t, i, j) {
     if (i < j) {
-      const double v = 0.5 * (M[i * ld + j] + M[j * ld + i]);
-      M[i * ld + j] = v;
-      M[j * ld + i] = v;
+      const double v = 0.5 * (B1[i * ld + j] + B1[j * ld + i]);
+      B1[i * ld + j] = v;
+      B1[j * ld + i] = v;
     }
   }
   __syncthreads();
-  // 4. eigendecomposition of Tt
-  const int sweeps = jacobi_eig(M, ld, U, ld, k, cs, flag + 1, 40, jac_tol);
-  sort_desc(M, ld, k, vals, perm);
-  // 5. S = D L^{-T} U_sorted: back substitution per column (into L's upper
-  //    part is not possible: write into M, sorted column order)
-  {
-    const int c = tid >> 2, part = tid & 3;
-    if (c < k) {
-      const int pc = perm[c];
-      for (int i = k - 1; i >= 0; --i) {
-        double sacc = 0.0;
-        for (int j = i + 1 + part; j < k; j += 4) sacc += L[j * ld + i] * M[j * ld + c];
-        sacc += __shfl_xor(sacc, 1);
-        sacc += __shfl_xor(sacc, 2);
-        const double v = (U[i * ld + pc] - sacc) / L[i * ld + i];
-        if (part == 0) M[i * ld + c] = v;
+  // eigendecomposition of the projected matrix (B1, nearly diagonal on the
+  // Newton path), eigenvectors in B2
+  sweeps = jacobi_eig(B1, ld, B2, ld, k, cs, flag + 1, 40, jac_tol, newton_ok,
+                      newton_ok ? imp : nullptr);
+  sort_desc(B1, ld, k, vals, perm);
+  if (newton_ok) {
+    // coefficients D X U[:, perm] into B0 (X^T G X is no longer needed)
+    strip_mm(B0, ld, Sg, KMAX, B2, ld, perm, d, k);
+    __syncthreads();
+    Sbuf = B0;
+    Pbuf = B1;
+    Ybuf = B3;
+  } else {
+    double* L = B0;
+    double* M = B1;
+    double* U = B2;
+    // S = D L^{-T} U_sorted: back substitution per column into M (sorted
+    // column order)
+    {
+      const int c = tid >> 2, part = tid & 3;
+      if (c < k) {
+        const int pc = perm[c];
+        for (int i = k - 1; i >= 0; --i) {
+          double sacc = 0.0;
+          for (int j = i + 1 + part; j < k; j += 4) sacc += L[j * ld + i] * M[j * ld + c];
+          sacc += __shfl_xor(sacc, 1);
+          sacc += __shfl_xor(sacc, 2);
+          const double v = (U[i * ld + pc] - sacc) / L[i * ld + i];
+          if (part == 0) M[i * ld + c] = v;
+        }
       }
     }
+    __syncthreads();
+    RR_FOR_KK(t, i, c) M[i * ld + c] *= d[i];
+    __syncthreads();
+    Sbuf = M;
+    Pbuf = U;
+    Ybuf = L;
+  }
+  // coefficients out; P into Pbuf for the residual product
+  RR_FOR_KK(t, i, c) {
+    Sg[i * KMAX + c] = Sbuf[i * ld + c];
+    Pbuf[i * ld + c] = 0.5 * (P[i * k + c] + P[c * k + i]);
   }
   __syncthreads();
-  double* S = small + SL::S;
-  for (int t = tid; t < kk; t += nt) {
-    const int i = t / k, c = t - (t / k) * k;
-    const double v = d[i] * M[i * ld + c];
-    M[i * ld + c] = v;             // M now holds S
-    S[i * KMAX + c] = v;
-  }
-  // P into U (LDS) for the residual product
-  for (int t = tid; t < kk; t += nt) {
-    const int i = t / k, j = t - (t / k) * k;
-    U[i * ld + j] = 0.5 * (P[i * k + j] + P[j * k + i]);
-  }
-  __syncthreads();
-  // 6. Y = P S (into L) on MFMA f64 16x16x4, then s_c^T P s_c = ||W v_c||^2.
-  {
-    typedef double d4v __attribute__((ext_vector_type(4)));
-    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-    const int m = lane & 15, kq = lane >> 4, kb = k / 16;
-    for (int blk = wave; blk < kb * kb; blk += nw) {
-      const int a0 = (blk / kb) * 16, b0 = (blk - (blk / kb) * kb) * 16;
-      d4v acc = {0.0, 0.0, 0.0, 0.0};
-      for (int q0 = 0; q0 < k; q0 += 4) {
-        const double av = U[(a0 + m) * ld + q0 + kq];
-        const double bv = M[(q0 + kq) * ld + b0 + m];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) L[(a0 + kq + 4 * v) * ld + b0 + m] = acc[v];
-    }
-  }
+  // Y = P S (MFMA), then s_c^T P s_c = ||W v_c||^2.
+  lds_mm(Ybuf, ld, Pbuf, ld, false, Sbuf, ld, k);
   __syncthreads();
   double* theta = small + SL::THETA;
   double* res = small + SL::RES;
@@ -370,7 +616,7 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
   }
   const double gam = filter ? fmax(fabs(vals[0] - fc), fe) : scale;
   for (int c = tid; c < k; c += nt) {
-    const double sps = lds_dot(M + c, ld, L + c, ld, k);
+    const double sps = lds_dot(Sbuf + c, ld, Ybuf + c, ld, k);
     const double th = vals[c];
     theta[c] = th;
     res[c] = sqrt(fmax(sps - th * th, 0.0)) / scale;
@@ -382,9 +628,8 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
     inv[c] = 1.0 / fmax(sqrt(fmax(nrm2, 0.0)), 1e-7 * gam);
   }
   __syncthreads();
-  for (int t = tid; t < kk; t += nt) {
-    const int i = t / k, c = t - (t / k) * k;
-    const double sv = M[i * ld + c] * inv[c];
+  RR_FOR_KK(t, i, c) {
+    const double sv = Sbuf[i * ld + c] * inv[c];
     small[SL::MZ + i * KMAX + c] = sv;
     small[SL::MB + i * KMAX + c] = -fc * sv;
   }
@@ -405,11 +650,15 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
     sc[S_FILTC] = fc;
     sc[S_FILTE] = fe;
     sc[S_SWEEPS] = (double)sweeps;
+    sc[S_RRPATH] = (double)path;
+    sc[S_RRCHOL] += (path < 0) ? 1.0 : 0.0;
+    sc[S_RRCOUNT] += 1.0;
     bool bad = false;
     for (int c = 0; c < k; ++c) bad |= !isfinite(vals[c]);
     if (bad) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 1.0);
   }
 }
+#undef RR_FOR_KK
 
 // Sums the per-slice Gram partials [B^T B, B^T Z, Z^T Z] into the GG/TG/PG
 // slots of `small` (one thread per entry, fixed summation order).

@@ -165,7 +165,8 @@ class Solver:
                                         out.size), "debug_scalars")
         names = {0: "alpha", 1: "lower_bound", 2: "maxres", 3: "lambda_r", 4: "lambda_r1",
                  5: "normw", 6: "eps_p", 7: "eps_d", 8: "obj", 9: "dual_obj", 10: "dx2",
-                 13: "nonfinite", 14: "dropped", 15: "filter_c", 16: "filter_e", 17: "sweeps"}
+                 13: "nonfinite", 14: "dropped", 15: "filter_c", 16: "filter_e", 17: "sweeps",
+                 18: "rr_newton_steps", 19: "rr_cholesky_calls", 20: "rr_calls"}
         d = {v: float(out[k]) for k, v in names.items()}
         d["theta"] = out[64:].tolist()
         return d
