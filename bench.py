@@ -7,6 +7,10 @@ device-side restart `proxsdp_reset` is inside the timed region; host
 preprocessing and the host-to-device upload happen once in `create`, outside
 it, and are reported as `setup_s`).
 
+`--iters K` replaces the solve by K iterations (short runs for hardware
+counters); `--copy-calibration MIB` first runs a plain device copy of that
+size, whose counter readings calibrate the HBM byte counters.
+
 Prints ONE JSON line on stdout.  Progress goes to stderr.
 """
 import argparse
@@ -20,6 +24,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6      # dense FP64 MFMA
+# HBM bytes per launch of the k = 64 dense pass from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, calibrated against a 256 MiB device copy (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0); see profiles/k_block_partial_f64_k_write_w_n5000_k64_hbm_counters.md.
+# Must be re-measured whenever k_block_partial_f64 changes.
+PASS_K64_TRAFFIC_BYTES = {"read": 227.8e6, "write": 31.1e6}
 
 
 def log(*a):
@@ -36,9 +46,12 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=1)
+    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--iters", type=int, default=0, help="run K iterations instead of a solve")
+    ap.add_argument("--copy-calibration", type=int, default=0, help="MiB of a plain device copy")
     ap.add_argument("--window", type=int, default=0, help="Algorithm 2 window l (0 = library default)")
     ap.add_argument("--eig-rel", type=float, default=0.0, help="eigen accuracy factor (0 = default)")
+    ap.add_argument("--r0", type=int, default=0, help="initial target rank (0 = default, 1)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -66,23 +79,35 @@ def main():
         opts["window"] = args.window
     if args.eig_rel:
         opts["eig_rel"] = args.eig_rel
+    if args.r0:
+        opts["r0"] = args.r0
     s = Solver(prob, device=dev, **opts)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"create (preprocess + upload + first eigensolve): {setup_s:.2f}s, workspace "
         f"{s.ws_bytes/2**20:.0f} MiB")
 
+    if args.copy_calibration:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_calibration} MiB")
+        del src, dst
+
     def one_solve(profile=False):
         check(lib.proxsdp_reset(s._h), "proxsdp_reset")
         if profile:
             check(lib.proxsdp_profile_enable(s._h, 1), "profile_enable")
-        info = s.solve()
+        info = s.step(args.iters) if args.iters else s.solve()
         prof = None
         if profile:
-            pm, pc, wm, wc = C.c_double(), C.c_int32(), C.c_double(), C.c_int32()
-            check(lib.proxsdp_profile_read(s._h, C.byref(pm), C.byref(pc), C.byref(wm),
-                                           C.byref(wc)), "profile_read")
-            prof = (pm.value, pc.value, wm.value, wc.value)
+            tot = np.zeros(8)
+            check(lib.proxsdp_profile_totals(s._h, tot.ctypes.data_as(C.POINTER(C.c_double)), 8),
+                  "profile_totals")
+            prof = tot
         return info, prof
 
     for w in range(args.warmup):
@@ -108,37 +133,46 @@ def main():
     dbg = s.debug()
     _, lam_f = s.factors()
     rank_x = int(np.sum(lam_f > 1e-8 * max(lam_f.max(), 1e-300))) if lam_f.size else 0
-    # roofline of the dominant kernel: the dense pass Z = W B (FP64 MFMA), bytes = 8 n^2 per launch
-    pass_ms = sum(p[0] for p in profs)
-    pass_cnt = sum(p[1] for p in profs)
-    write_ms = sum(p[2] for p in profs)
-    write_cnt = sum(p[3] for p in profs)
-    pass_avg_s = pass_ms / max(pass_cnt, 1) / 1000.0
-    write_avg_s = write_ms / max(write_cnt, 1) / 1000.0
-    bytes_pass = 8.0 * n * n
-    achieved = bytes_pass / pass_avg_s / 1e9 if pass_avg_s > 0 else 0.0
-    write_gbs = bytes_pass / write_avg_s / 1e9 if write_avg_s > 0 else 0.0
-    roofline = {
+    tot = np.sum(np.array(profs), axis=0)
+    pass_s, pass_cnt, pass_flops, pass_bytes = tot[0] / 1e3, int(tot[1]), tot[2], tot[3]
+    write_s, write_cnt, write_flops, write_bytes = tot[4] / 1e3, int(tot[5]), tot[6], tot[7]
+    # Dominant sweep kernel: the dense pass Z = W B (FP64 MFMA).  Its bound is
+    # the MFMA peak when its arithmetic intensity (k/4 flop/B) is above the
+    # FP64 ridge (78.6 TFLOP/s / 8 TB/s = 9.8 flop/B, i.e. k > 39), else HBM.
+    intensity = pass_flops / max(pass_bytes, 1.0)
+    ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    gbs = pass_bytes / max(pass_s, 1e-12) / 1e9
+    tfs = pass_flops / max(pass_s, 1e-12) / 1e12
+    if intensity > ridge:
+        roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tfs / PEAK_FP64_TFLOPS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    roofline = dict(roof)
+    roofline.update({
+        "traffic": (PASS_K64_TRAFFIC_BYTES["read"] + PASS_K64_TRAFFIC_BYTES["write"]
+                    if n == 5000 else None),
+        "traffic_note": "HBM bytes per k=64 launch (read 227.8 MB + write 31.1 MB, rocprofv3 "
+                        "FETCH_SIZE/WRITE_SIZE, copy-calibrated) vs 204.5 MB algorithmic read",
         "kernel": "k_block_partial_f64 (dense pass W B, FP64 MFMA)",
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": PEAK_HBM_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / PEAK_HBM_GBS, 4),
-        "traffic": None,
-        "bytes_per_launch": bytes_pass,
-        "avg_launch_us": round(pass_avg_s * 1e6, 2),
         "launches": pass_cnt,
-        "unique_entry_GBps": round(8.0 * n * (n + 1) / 2 / pass_avg_s / 1e9, 1) if pass_avg_s else 0,
-        "write_kernel": {"name": "k_write_w", "achieved": round(write_gbs, 1),
-                         "avg_launch_us": round(write_avg_s * 1e6, 2), "launches": write_cnt},
-        "sweep_share_of_solve": round((pass_ms + write_ms) / 1000.0 / max(sum(times), 1e-9), 3),
-    }
+        "avg_launch_us": round(pass_s / max(pass_cnt, 1) * 1e6, 2),
+        "flops_per_launch": round(pass_flops / max(pass_cnt, 1)),
+        "bytes_per_launch": round(pass_bytes / max(pass_cnt, 1)),
+        "intensity_flop_per_byte": round(intensity, 2),
+        "hbm_GBps": round(gbs, 1),
+        "write_kernel": {"name": "k_write_w", "launches": write_cnt,
+                         "avg_launch_us": round(write_s / max(write_cnt, 1) * 1e6, 2),
+                         "GBps": round(write_bytes / max(write_s, 1e-12) / 1e9, 1),
+                         "TFLOPs": round(write_flops / max(write_s, 1e-12) / 1e12, 2)},
+        "sweep_share_of_solve": round((pass_s + write_s) / max(sum(times), 1e-9), 3),
+    })
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, last["iters"], args.cpu_iters)
     out = {
-        "metric": "time-to-1e-4 residual (s), max-cut G(5000,0.01), plain FP64 LR-PD-SDP",
+        "metric": "time-to-1e-4 residual (s)" if not args.iters else f"time for {args.iters} iterations (s)",
         "value": round(sum(times) / len(times), 4),
         "unit": "s",
         "n_gpus": 1,
@@ -151,7 +185,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded Erdos-Renyi graph, unit weights)",
         "config": {
-            "workload": f"maxcut_G({n},{args.p})_seed{args.seed}_fp64_lr",
+            "workload": f"maxcut G({n},{args.p}) seed {args.seed}, plain FP64 LR-PD-SDP to 1e-4",
             "n": n, "edges": int(prob.meta["edges"]), "tol": args.tol,
             "iters": last["iters"], "final_rank": last["r"], "passes": last["passes"],
             "obj": last["obj"], "rho_p": last["rho_p"], "rho_d": last["rho_d"],

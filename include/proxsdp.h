@@ -113,7 +113,7 @@ typedef struct {
                            kept Ritz pairs meet eig_tol (synchronises per round;
                            for verification), 0 (default): adaptive schedule    */
   double eig_rel;       /* adaptive schedule: target relative Ritz residual
-                           max(eig_tol, eig_rel * max(rho_p, rho_d)) (default 0.05) */
+                           max(eig_tol, eig_rel * max(rho_p, rho_d)) (default 0.2) */
 } proxsdp_options;
 
 /* ------------------------------------------------------------- info */
@@ -187,6 +187,15 @@ int proxsdp_reset(proxsdp_handle *h);
 int proxsdp_profile_enable(proxsdp_handle *h, int32_t enable);
 int proxsdp_profile_read(proxsdp_handle *h, double *pass_ms, int32_t *pass_count,
                          double *write_ms, int32_t *write_count);
+
+/* Kernel timing totals since proxsdp_profile_enable (synchronises, disables
+ * profiling): out[0] summed dense-pass time (ms), out[1] timed passes,
+ * out[2] their algorithmic flops (2 npad^2 k per pass, k its subspace width),
+ * out[3] their algorithmic bytes (8 npad^2 per pass, one read of W),
+ * out[4] summed dense-write time (ms), out[5] timed writes, out[6] their MFMA
+ * flops (2 r per cell of the upper tile pairs), out[7] their bytes (8 n^2
+ * written).  Copies min(count, 8) values to the host array `out`. */
+int proxsdp_profile_totals(proxsdp_handle *h, double *out, int32_t count);
 
 /* Rank path of Algorithm 2 since create/reset: for each change of the target
  * rank, the iteration after which it happened, the new rank and the reason

@@ -468,6 +468,7 @@ struct proxsdp_handle {
   // optional kernel timing (benchmarks)
   bool prof = false;
   std::vector<hipEvent_t> ev_pass, ev_write;   // start/stop pairs
+  std::vector<int> prof_k, prof_r;             // subspace width / rank of each timed launch
   int n_pass = 0, n_write = 0;
   ~proxsdp_handle() {
     for (auto e : ev_pass) (void)hipEventDestroy(e);
@@ -482,6 +483,10 @@ static void prof_mark(proxsdp_handle* H, std::vector<hipEvent_t>& pool, int& cnt
   const int idx = 2 * cnt + (start ? 0 : 1);
   if (cnt >= PROF_MAX || idx >= (int)pool.size()) return;
   (void)hipEventRecord(pool[idx], H->st);
+  if (start) {
+    if (&pool == &H->ev_pass) H->prof_k.push_back(H->k);
+    else H->prof_r.push_back(H->r);
+  }
   if (!start) ++cnt;
 }
 
@@ -1037,7 +1042,7 @@ int proxsdp_default_options(proxsdp_options* o) {
   o->max_passes = 8;
   o->seed = 1;
   o->eig_strict = 0;
-  o->eig_rel = 0.05;
+  o->eig_rel = 0.2;
   return PROXSDP_OK;
 }
 
@@ -1372,6 +1377,37 @@ int proxsdp_profile_enable(proxsdp_handle* H, int32_t enable) {
   H->prof = enable != 0;
   H->n_pass = 0;
   H->n_write = 0;
+  H->prof_k.clear();
+  H->prof_r.clear();
+  return PROXSDP_OK;
+}
+
+int proxsdp_profile_totals(proxsdp_handle* H, double* out, int32_t count) {
+  g_err.clear();
+  if (!H || !out) return fail(PROXSDP_ERR_INVALID, "handle or out is NULL");
+  HIP_OK(hipStreamSynchronize(H->st));
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const double np2 = (double)H->npad * H->npad, n2 = (double)H->n * H->n;
+  const int ts = H->npad / TILE;
+  const double pair_cells = (double)ts * (ts + 1) / 2 * TILE * TILE;
+  for (int i = 0; i < H->n_pass; ++i) {
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, H->ev_pass[2 * i], H->ev_pass[2 * i + 1]));
+    v[0] += ms;
+    v[2] += 2.0 * np2 * (i < (int)H->prof_k.size() ? H->prof_k[i] : H->k);
+    v[3] += 8.0 * np2;
+  }
+  for (int i = 0; i < H->n_write; ++i) {
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, H->ev_write[2 * i], H->ev_write[2 * i + 1]));
+    v[4] += ms;
+    v[6] += 2.0 * pair_cells * (i < (int)H->prof_r.size() ? H->prof_r[i] : H->r);
+    v[7] += 8.0 * n2;
+  }
+  v[1] = H->n_pass;
+  v[5] = H->n_write;
+  for (int i = 0; i < count && i < 8; ++i) out[i] = v[i];
+  H->prof = false;
   return PROXSDP_OK;
 }
 
