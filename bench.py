@@ -52,6 +52,10 @@ def main():
     ap.add_argument("--window", type=int, default=0, help="Algorithm 2 window l (0 = library default)")
     ap.add_argument("--eig-rel", type=float, default=0.0, help="eigen accuracy factor (0 = default)")
     ap.add_argument("--r0", type=int, default=0, help="initial target rank (0 = default, 1)")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="storage of W for the timed steps (fp32 = precision form)")
+    ap.add_argument("--no-precision-form", action="store_true",
+                    help="skip the FP32 precision-form solve reported beside the FP64 result")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -81,7 +85,10 @@ def main():
         opts["eig_rel"] = args.eig_rel
     if args.r0:
         opts["r0"] = args.r0
-    s = Solver(prob, device=dev, **opts)
+    main_opts = dict(opts)
+    if args.precision == "fp32":
+        main_opts["precision"] = 1
+    s = Solver(prob, device=dev, **main_opts)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"create (preprocess + upload + first eigensolve): {setup_s:.2f}s, workspace "
@@ -168,6 +175,9 @@ def main():
                          "TFLOPs": round(write_flops / max(write_s, 1e-12) / 1e12, 2)},
         "sweep_share_of_solve": round((pass_s + write_s) / max(sum(times), 1e-9), 3),
     })
+    prec = None
+    if not args.no_precision_form and not args.iters and args.precision == "fp64":
+        prec = precision_form(prob, dev, opts, sum(times) / len(times), last)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, last["iters"], args.cpu_iters)
@@ -194,10 +204,48 @@ def main():
             "rr_calls": int(dbg["rr_calls"]), "rr_cholesky_calls": int(dbg["rr_cholesky_calls"]),
         },
         "roofline": roofline,
+        "precision_form": prec,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     s.close()
+
+
+def precision_form(prob, dev, opts, t64, info64):
+    """One solve of the precision form (FP32 W, FP32 MFMA filter passes, exact
+    FP64 Rayleigh-Ritz passes) of the same instance, timed like the FP64 steps,
+    with its error against the plain FP64 GPU answer."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    from paper_1810_05231_amd import Solver
+    from paper_1810_05231_amd._lib import check, lib
+    s = Solver(prob, device=dev, precision=1, **opts)
+    check(lib.proxsdp_reset(s._h), "proxsdp_reset")
+    check(lib.proxsdp_profile_enable(s._h, 1), "profile_enable")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = s.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tot = np.zeros(8)
+    check(lib.proxsdp_profile_totals(s._h, tot.ctypes.data_as(C.POINTER(C.c_double)), 8),
+          "profile_totals")
+    log(f"precision form (fp32): {info['status_name']} iters={info['iters']} r={info['r']} "
+        f"passes={info['passes']} wall={dt:.3f}s obj={info['obj']:.8f}")
+    out = {
+        "form": "FP32 dense W (FP32 MFMA filter passes) + exact FP64 Rayleigh-Ritz passes",
+        "value": round(dt, 4), "unit": "s", "status": info["status_name"],
+        "iters": info["iters"], "passes": info["passes"], "final_rank": info["r"],
+        "obj": info["obj"], "rho_p": info["rho_p"], "rho_d": info["rho_d"],
+        "obj_rel_diff_vs_fp64": abs(info["obj"] - info64["obj"]) / abs(info64["obj"]),
+        "speedup_vs_fp64": round(t64 / dt, 3),
+        "fp32_pass_avg_us": round(tot[0] / max(tot[1], 1) * 1e3, 2),
+        "fp32_pass_launches": int(tot[1]),
+        "fp32_write_avg_us": round(tot[4] / max(tot[5], 1) * 1e3, 2),
+    }
+    s.close()
+    return out
 
 
 def cpu_baseline(prob, gpu_iters, iters):

@@ -100,7 +100,14 @@ typedef struct {
   int32_t r0;           /* initial target rank (default 1, Algorithm 2)          */
   int32_t r_max;        /* largest target rank (0 = automatic)                   */
   int32_t full_eig;     /* 1 = PD-SDP (Algorithm 1, exact projection; n <= 64)   */
-  int32_t precision;    /* PROXSDP_FP64 (default), PROXSDP_FP32, PROXSDP_BF16    */
+  int32_t precision;    /* storage of the dense iterate W: PROXSDP_FP64 (default,
+                           plain form), PROXSDP_FP32 or PROXSDP_BF16 (precision
+                           form: Chebyshev filter passes over the low-precision W
+                           on FP32 / BF16 MFMA; every Rayleigh-Ritz pass applies W
+                           exactly in FP64 from the factors of X, the sparse part
+                           and the rank-one terms; factors, Rayleigh-Ritz,
+                           residuals and the dual step stay FP64).  The exact
+                           small-n path (n <= 64 or full_eig) always uses FP64. */
   int32_t max_iters;    /* default 200000                                        */
   double time_limit_s;  /* default 1200 (the paper's cap); <= 0 = none           */
   int32_t row_scaling;  /* 1 (default): rows scaled to unit Frobenius norm        */
@@ -191,10 +198,10 @@ int proxsdp_profile_read(proxsdp_handle *h, double *pass_ms, int32_t *pass_count
 /* Kernel timing totals since proxsdp_profile_enable (synchronises, disables
  * profiling): out[0] summed dense-pass time (ms), out[1] timed passes,
  * out[2] their algorithmic flops (2 npad^2 k per pass, k its subspace width),
- * out[3] their algorithmic bytes (8 npad^2 per pass, one read of W),
- * out[4] summed dense-write time (ms), out[5] timed writes, out[6] their MFMA
- * flops (2 r per cell of the upper tile pairs), out[7] their bytes (8 n^2
- * written).  Copies min(count, 8) values to the host array `out`. */
+ * out[3] their algorithmic bytes (s npad^2 per pass, one read of W stored
+ * with s bytes per element: 8 FP64, 4 FP32, 2 BF16), out[4] summed
+ * dense-write time (ms), out[5] timed writes, out[6] their MFMA flops (2 r
+ * per cell of the upper tile pairs), out[7] their bytes (s n^2 written).  Copies min(count, 8) values to the host array `out`. */
 int proxsdp_profile_totals(proxsdp_handle *h, double *out, int32_t count);
 
 /* Rank path of Algorithm 2 since create/reset: for each change of the target

@@ -70,6 +70,89 @@ __global__ __launch_bounds__(256) void k_block_partial_f64(
   }
 }
 
+// FP32 form of the pass for W stored in single precision (precision form):
+// W and the basis entries are FP32 operands of MFMA f32 16x16x4 (FP32
+// accumulation over the rows of one chunk); the chunk partials are written in
+// FP64 and summed in FP64 by k_reduce_gram.  Operand layout as in the FP64
+// kernel; the FP32 accumulator holds D[4 (l / 16) + v][l % 16].
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <int KB>
+__global__ __launch_bounds__(256) void k_block_partial_f32(
+    const float* __restrict__ W, int64_t ld, const double* __restrict__ B, int ldk,
+    double* __restrict__ part, int rows_per_chunk, int npad) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + wave * 16 + (lane & 15);
+  const int chunk = blockIdx.y;
+  const int j0 = chunk * rows_per_chunk;
+  const int j1 = min(j0 + rows_per_chunk, npad);
+  const int lrow = lane >> 4;
+  f4 acc[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) acc[kb] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int j = j0; j < j1; j += 64) {
+    float w[16];
+    float a[16][KB];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) w[u] = W[(int64_t)(j + 4 * u + lrow) * ld + col];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int row = j + 4 * u + lrow;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) a[u][kb] = (float)B[(int64_t)row * ldk + kb * 16 + (lane & 15)];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+        acc[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][kb], w[u], acc[kb], 0, 0, 0);
+    }
+  }
+  double* out = part + (int64_t)chunk * npad * ldk + (int64_t)col * ldk;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[kb * 16 + 4 * lrow + v] = (double)acc[kb][v];
+  }
+}
+
+// Chebyshev step on an exactly applied product Z = W B (precision form, when
+// the low-precision pass is not accurate enough for the current target):
+//   mode 1: Bn = (Z - c B) / e;   mode 2: Bn = 2 (Z - c B) / e - Bprev
+// c, e are read from the device (centre and half-width of the last
+// Rayleigh-Ritz step).
+__global__ __launch_bounds__(256) void k_cheb_combine(const double* __restrict__ Z,
+                                                      const double* __restrict__ B,
+                                                      const double* __restrict__ Bprev,
+                                                      double* __restrict__ Bn, int64_t count,
+                                                      int mode, const double* __restrict__ filt) {
+  const double cc = filt[0], ce = filt[1];
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const double z = (Z[t] - cc * B[t]) / ce;
+    Bn[t] = (mode == 2) ? 2.0 * z - Bprev[t] : z;
+  }
+}
+
+// Round to nearest even of an FP64 value to bfloat16 (through FP32, itself
+// round to nearest even); NaN stays a quiet NaN.
+__device__ __forceinline__ unsigned short to_bf16_rne(double x) {
+  const float f = (float)x;
+  unsigned int u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x0040u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+template <typename T>
+__device__ __forceinline__ T store_cast(double x);
+template <>
+__device__ __forceinline__ double store_cast<double>(double x) { return x; }
+template <>
+__device__ __forceinline__ float store_cast<float>(double x) { return (float)x; }
+template <>
+__device__ __forceinline__ unsigned short store_cast<unsigned short>(double x) { return to_bf16_rne(x); }
+
 // Gram partials of one SLICE-row block on MFMA f64 16x16x4:
 //   out[0] = X^T X, out[1] = X^T Y, out[2] = Y^T Y  (k x k each, row-major),
 // X, Y: SLICE x k in LDS (row stride k).  Output blocks of 16 x 16 are dealt
@@ -100,6 +183,7 @@ __device__ inline void gram_blocks_mfma(const double* X, const double* Y, int k,
 
 // Sums partials into Z, optional Chebyshev step, Gram partials per slice.
 //   cheb 0: Z = W B;   1: Z = (W B - c B) / e;   2: Z = 2 (W B - c B) / e - Bprev
+// Z == nullptr: Z is not stored (Gram partials of a product that already exists).
 __global__ __launch_bounds__(256) void k_reduce_gram(const double* __restrict__ part, int nchunks,
                                                      double* __restrict__ Z,
                                                      const double* __restrict__ B,
@@ -127,7 +211,7 @@ __global__ __launch_bounds__(256) void k_reduce_gram(const double* __restrict__ 
       z = (z - cc * b) / ce;
     else if (cheb == 2)
       z = 2.0 * (z - cc * b) / ce - Bprev[off];
-    Z[off] = z;
+    if (Z) Z[off] = z;
     sZ[t] = z;
     sB[t] = b;
   }
@@ -269,11 +353,10 @@ __global__ __launch_bounds__(256) void k_rowwise(const double* __restrict__ B,
 // with X = V diag(lam) V^T the current factors, D = -alpha C + alpha M*(y) on the
 // sparsity pattern (the values the dense write adds) and gamma_q = alpha sigma_q y_q.
 // Z = W B is applied exactly in FP64 without the dense matrix:
-//   k_vtb           per-slice partials of V^T B (rp x k) and u_q^T B
-//   k_sum_vb        slice sums into small[VB]
-//   k_implicit_apply  Z rows = V_i (lam o V^T B) + sum_{e in row i} D_e B_other(e)
-//                   + sum_q gamma_q u_q[i] (u_q^T B), then the Rayleigh-Ritz Gram
-//                   partials [B^T B, B^T Z, Z^T Z] of the slice.
+//   k_vtb            per-slice partials of V^T B (r x k) and u_q^T B (MFMA)
+//   k_sum_vb         slice sums, scaled by lambda_t and gamma_q
+//   k_implicit_rows  Z_i = V_i M + sum_q u_q[i] M_q + sum_{e in row i} D_e B_other(e)
+// and the Rayleigh-Ritz Gram partials come from k_reduce_gram on Z.
 __global__ __launch_bounds__(256) void k_vtb(const double* __restrict__ V, int r,
                                              const double* __restrict__ B, int k, int n_r1,
                                              const double* __restrict__ r1_u, int npad,
@@ -307,85 +390,67 @@ __global__ __launch_bounds__(256) void k_vtb(const double* __restrict__ V, int r
   }
 }
 
+// Slice sums of the V^T B and u^T B partials, scaled for the apply:
+//   small[VB + t KMAX + c]          = lambda_t (V^T B)_tc          (t < r)
+//   small[VB + KMAX^2 + q KMAX + c] = gamma_q (u_q^T B)_c,  gamma_q = alpha sigma_q y_row(q)
 __global__ __launch_bounds__(256) void k_sum_vb(const double* __restrict__ vb_part, int nslices,
-                                                int r, int k, int n_r1, double* __restrict__ small) {
+                                                int r, int k, DevProblem dp,
+                                                const double* __restrict__ y, int lam_off,
+                                                double* __restrict__ small) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int n1 = r * k;
-  if (t >= n1 + n_r1 * k) return;
-  const int src = (t < n1) ? (t / k) * KMAX + (t - (t / k) * k)
-                           : KMAX * KMAX + ((t - n1) / k) * KMAX + ((t - n1) - ((t - n1) / k) * k);
+  if (t >= n1 + dp.n_r1 * k) return;
+  int src;
+  double sc;
+  if (t < n1) {
+    const int a = t / k;
+    src = a * KMAX + (t - a * k);
+    sc = small[lam_off + a];
+  } else {
+    const int q = (t - n1) / k;
+    src = KMAX * KMAX + q * KMAX + (t - n1 - q * k);
+    sc = small[SL::SC + S_ALPHA] * dp.r1_sigma[q] * y[dp.r1_row[q]];
+  }
   double acc = 0.0;
 #pragma unroll 8
   for (int s = 0; s < nslices; ++s) acc += vb_part[(int64_t)s * VB_STRIDE + src];
-  small[SL::VB + src] = acc;
+  small[SL::VB + src] = sc * acc;
 }
 
-__global__ __launch_bounds__(256) void k_implicit_apply(DevProblem dp, const double* __restrict__ V,
-                                                        int r, const double* __restrict__ small,
-                                                        int lam_off, const double* __restrict__ y,
-                                                        const double* __restrict__ dval,
-                                                        const double* __restrict__ B, int k,
-                                                        double* __restrict__ Z,
-                                                        double* __restrict__ gram_part) {
-  extern __shared__ double sm[];
-  double* sB = sm;                      // SLICE x k
-  double* sZ = sB + SLICE * k;          // SLICE x k
-  double* sM = sZ + SLICE * k;          // r x k   lam o V^T B
-  double* sU = sM + (r > 0 ? r : 1) * k;  // n_r1 x k  gamma o u^T B
-  const int s = blockIdx.x;
-  const int i0 = s * SLICE;
-  const double* lam = small + lam_off;
-  const double alpha = small[SL::SC + S_ALPHA];
-  for (int t = threadIdx.x; t < r * k; t += blockDim.x) {
-    const int a = t / k, c = t - (t / k) * k;
-    sM[t] = lam[a] * small[SL::VB + a * KMAX + c];
-  }
-  for (int t = threadIdx.x; t < dp.n_r1 * k; t += blockDim.x) {
-    const int q = t / k, c = t - (t / k) * k;
-    sU[t] = alpha * dp.r1_sigma[q] * y[dp.r1_row[q]] * small[SL::VB + KMAX * KMAX + q * KMAX + c];
-  }
-  for (int t = threadIdx.x; t < SLICE * k; t += blockDim.x) sB[t] = B[(int64_t)i0 * k + t];
-  __syncthreads();
-  // thread -> (row, column chunk)
-  const int cpt = (k + 3) / 4;                     // columns per thread
-  const int row = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * cpt;
-  const int gi = i0 + row;
-  double acc[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-  if (gi < dp.n) {
-    for (int t = 0; t < r; ++t) {
-      const double v = V[(int64_t)gi * KMAX + t];
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (u < cpt && c0 + u < k) acc[u] += v * sM[t * k + c0 + u];
+// Z = W B applied exactly (rows of the precision form's Rayleigh-Ritz pass):
+//   Z_i = sum_t V_it M_t + sum_q u_q[i] M_q + sum_{e in row i} D_e B_other(e)
+// with M from k_sum_vb.  A workgroup covers 4 rows, a thread one column.
+__global__ __launch_bounds__(256) void k_implicit_rows(DevProblem dp, const double* __restrict__ V,
+                                                       int r, const double* __restrict__ small,
+                                                       const double* __restrict__ dval,
+                                                       const double* __restrict__ B, int k,
+                                                       double* __restrict__ Z) {
+  const int c = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= k || i >= dp.npad) return;
+  double acc = 0.0;
+  if (i < dp.n) {
+    const double* M = small + SL::VB;
+    const double* vrow = V + (int64_t)i * KMAX;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int t = 0;
+    for (; t + 3 < r; t += 4) {
+      a0 += vrow[t] * M[t * KMAX + c];
+      a1 += vrow[t + 1] * M[(t + 1) * KMAX + c];
+      a2 += vrow[t + 2] * M[(t + 2) * KMAX + c];
+      a3 += vrow[t + 3] * M[(t + 3) * KMAX + c];
     }
-    for (int q = 0; q < dp.n_r1; ++q) {
-      const double uv = dp.r1_u[(int64_t)q * dp.npad + gi];
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (u < cpt && c0 + u < k) acc[u] += uv * sU[q * k + c0 + u];
-    }
-    for (int e0 = dp.sym_ptr[gi]; e0 < dp.sym_ptr[gi + 1]; ++e0) {
+    for (; t < r; ++t) a0 += vrow[t] * M[t * KMAX + c];
+    acc = (a0 + a1) + (a2 + a3);
+    for (int q = 0; q < dp.n_r1; ++q)
+      acc += dp.r1_u[(int64_t)q * dp.npad + i] * M[KMAX * KMAX + q * KMAX + c];
+    for (int e0 = dp.sym_ptr[i]; e0 < dp.sym_ptr[i + 1]; ++e0) {
       const int e = dp.sym_e[e0];
       const int ea = dp.pat_a[e], eb = dp.pat_b[e];
-      const int other = (ea == gi) ? eb : ea;
-      const double dv = dval[e];
-      const double* brow = B + (int64_t)other * k + c0;
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (u < cpt && c0 + u < k) acc[u] += dv * brow[u];
+      acc += dval[e] * B[(int64_t)((ea == i) ? eb : ea) * k + c];
     }
   }
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    if (u < cpt && c0 + u < k) {
-      sZ[row * k + c0 + u] = acc[u];
-      Z[(int64_t)gi * k + c0 + u] = acc[u];
-    }
-  }
-  __syncthreads();
-  gram_blocks_mfma(sB, sZ, k, gram_part + (int64_t)s * 3 * k * k);
+  Z[(int64_t)i * k + c] = acc;
 }
 
 // Fills rows < n of an npad x ldk block (columns [c0, c1)) with uniform(-1, 1)
@@ -443,7 +508,8 @@ struct FinArgs {
 __device__ void finalize_iteration(const FinArgs& f, double* small, const DevProblem& dp,
                                    const double* y, const double* y_old, double* red);
 
-__global__ __launch_bounds__(256) void k_write_w(double* __restrict__ W, int64_t ld, int n,
+template <typename OutT>
+__global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t ld, int n,
                                                  const double* __restrict__ V, int ldv, int r,
                                                  double* __restrict__ small, int lam_off,
                                                  DevProblem dp, const double* __restrict__ y,
@@ -453,13 +519,13 @@ __global__ __launch_bounds__(256) void k_write_w(double* __restrict__ W, int64_t
                                                  int tiles_side) {
   extern __shared__ double sm[];
   const int T = tiles_side;
-  const int npairs = T * (T + 1) / 2;
-  if ((int)blockIdx.x >= npairs) {
-    if (has_fin) finalize_iteration(fin, small, dp, y, y_old, sm);
+  // block 0 finalises the iteration (scheduled first, so that it overlaps the tiles)
+  if (has_fin && blockIdx.x == 0) {
+    finalize_iteration(fin, small, dp, y, y_old, sm);
     return;
   }
   // block -> tile pair (I, J), I <= J, row-major over the upper triangle of tiles
-  const int idx = blockIdx.x;
+  const int idx = (int)blockIdx.x - (has_fin ? 1 : 0);
   auto first = [&](int i) { return i * T - (i * (i - 1)) / 2; };
   const double tt = 2.0 * T + 1.0;
   int I = (int)((tt - sqrt(fmax(tt * tt - 8.0 * idx, 0.0))) * 0.5);
@@ -540,13 +606,13 @@ __global__ __launch_bounds__(256) void k_write_w(double* __restrict__ W, int64_t
   for (int q = 0; q < TILE / 4; ++q) {
     const int a = w + 4 * q;
     const int ga = a0 + a, gb = b0 + c;
-    if (ga < n && gb < n) W[(int64_t)ga * ld + gb] = sT[a * (TILE + 1) + c];
+    if (ga < n && gb < n) W[(int64_t)ga * ld + gb] = store_cast<OutT>(sT[a * (TILE + 1) + c]);
   }
   if (I != J) {
     for (int q = 0; q < TILE / 4; ++q) {
       const int b = w + 4 * q;
       const int gb = b0 + b, ga = a0 + c;
-      if (gb < n && ga < n) W[(int64_t)gb * ld + ga] = sT[c * (TILE + 1) + b];
+      if (gb < n && ga < n) W[(int64_t)gb * ld + ga] = store_cast<OutT>(sT[c * (TILE + 1) + b]);
     }
   }
 }

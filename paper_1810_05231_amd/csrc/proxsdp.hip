@@ -113,8 +113,10 @@ int validate(const proxsdp_problem* pb, const proxsdp_options* o) {
     if (!(o->tol > 0)) return fail(PROXSDP_ERR_INVALID, "tol must be > 0");
     if (o->check_every < 1 || o->window < o->check_every || o->window % o->check_every)
       return fail(PROXSDP_ERR_INVALID, "window must be a positive multiple of check_every");
-    if (o->precision != PROXSDP_FP64)
-      return fail(PROXSDP_ERR_UNSUPPORTED, "only PROXSDP_FP64 storage is built in this library");
+    if (o->precision != PROXSDP_FP64 && o->precision != PROXSDP_FP32 && o->precision != PROXSDP_BF16)
+      return fail(PROXSDP_ERR_INVALID, "precision must be PROXSDP_FP64, PROXSDP_FP32 or PROXSDP_BF16");
+    if (o->precision == PROXSDP_BF16)
+      return fail(PROXSDP_ERR_UNSUPPORTED, "BF16 storage of W is not built yet");
     if (o->alpha < 0) return fail(PROXSDP_ERR_INVALID, "alpha must be >= 0");
     if (o->full_eig && pb->n > KMAX)
       return fail(PROXSDP_ERR_UNSUPPORTED, "full_eig needs n <= " + std::to_string(KMAX));
@@ -442,7 +444,11 @@ struct proxsdp_handle {
   Chunking ch{};
   int nsl = 1, nrow_blocks = 1, npat_blocks = 1;
   // device buffers
-  double* W = nullptr;
+  int prec = PROXSDP_FP64;   // storage of W: FP64 (plain form), FP32 or BF16 (precision form)
+  int wbytes = 8;            // bytes per stored element of W
+  double* W = nullptr;       // FP64 W (plain form and the exact small-n path)
+  void* Wl = nullptr;        // FP32 / BF16 W (precision form)
+  double* vb_part = nullptr; // per-slice partials of V^T B, u^T B (implicit operator)
   double* B[3] = {nullptr, nullptr, nullptr};
   int bcur = 0;
   double* Z = nullptr;
@@ -494,7 +500,14 @@ static size_t carve(proxsdp_handle* H, void* ws) {
   const int npad = H->npad;
   Carver c(ws);
   const Host& h = H->h;
-  H->W = c.take<double>((size_t)npad * npad);
+  if (H->prec == PROXSDP_FP64) {
+    H->W = c.take<double>((size_t)npad * npad);
+    H->Wl = nullptr;
+  } else {
+    H->W = nullptr;
+    H->Wl = c.take<char>((size_t)npad * npad * H->wbytes);
+  }
+  H->vb_part = c.take<double>((size_t)std::max(H->nsl, 1) * VB_STRIDE);
   H->B[0] = c.take<double>((size_t)npad * H->k_cap);
   H->B[1] = c.take<double>((size_t)npad * H->k_cap);
   H->B[2] = c.take<double>((size_t)npad * H->k_cap);
@@ -542,6 +555,9 @@ static void setup_dims(proxsdp_handle* H) {
   H->npad = h.npad;
   H->rows = h.rows;
   H->full = H->opt.full_eig || h.n <= KMAX;
+  // the exact small-n path reads W in FP64
+  H->prec = H->full ? PROXSDP_FP64 : H->opt.precision;
+  H->wbytes = H->prec == PROXSDP_FP64 ? 8 : (H->prec == PROXSDP_FP32 ? 4 : 2);
   if (H->full) {
     H->r_cap = h.n;
     H->k_cap = 16;
@@ -614,7 +630,9 @@ static int set_lds_limits() {
   if ((rc = set_lds_one((const void*)k_small_rr))) return rc;
   if ((rc = set_lds_one((const void*)k_rowwise))) return rc;
   if ((rc = set_lds_one((const void*)k_full_eig))) return rc;
-  if ((rc = set_lds_one((const void*)k_write_w))) return rc;
+  if ((rc = set_lds_one((const void*)k_write_w<double>))) return rc;
+  if ((rc = set_lds_one((const void*)k_write_w<float>))) return rc;
+  if ((rc = set_lds_one((const void*)k_write_w<unsigned short>))) return rc;
   done = true;
   return PROXSDP_OK;
 }
@@ -656,7 +674,7 @@ static void launch_reduce(const double* part, int nchunks, double* Z, const doub
 // jac_tol: relative off-diagonal level at which the Jacobi sweeps stop.
 // oa_steps: largest number of Newton refinement steps before the Cholesky path.
 static void launch_rr(const double* gram_part, int nsl, double* small, int k, int r, int lam_off,
-                      int filter, double jac_tol, hipStream_t st, int oa_steps = 5) {
+                      int filter, double jac_tol, hipStream_t st, int oa_steps = 10) {
   const int kk = k * k;
   hipLaunchKernelGGL(k_sum_grams, dim3((3 * kk + 255) / 256), dim3(256), 0, st, gram_part, nsl, k,
                      small);
@@ -682,18 +700,63 @@ static void launch_full(proxsdp_handle* H, double* V, int r, const double* Vold,
                      Vold, r_old, H->small, lam_off, H->dp.n_r1, H->dp.r1_u, H->npad, H->fac_part);
 }
 
-static void launch_write(proxsdp_handle* H, double* Wout, int64_t ld, const double* V, int r,
-                         int lam_off, bool sparse, bool rank1, const FinArgs* fin) {
+static int lam_slot(int parity) { return SL::LAM + parity * KMAX; }
+
+// Dense write of V diag(lambda+) V^T (+ rank-one terms, + the sparse part) into
+// Wout, stored as `out_prec` (FP64 for outputs, the handle's storage for W).
+static void launch_write(proxsdp_handle* H, void* Wout, int out_prec, int64_t ld, const double* V,
+                         int r, int lam_off, bool sparse, bool rank1, const FinArgs* fin) {
   const int ts = H->npad / TILE;
   const size_t lds = (size_t)TILE * (TILE + 1) * sizeof(double);
   FinArgs f{};
   if (fin) f = *fin;
-  hipLaunchKernelGGL(k_write_w, dim3(ts * (ts + 1) / 2 + (fin ? 1 : 0)), dim3(256), lds, H->st, Wout, ld,
-                     H->n, V, KMAX, r, H->small, lam_off, H->dp, H->y, H->y_old, H->dval,
-                     sparse ? 1 : 0, rank1 ? 1 : 0, fin ? 1 : 0, f, ts);
+  const dim3 grid(ts * (ts + 1) / 2 + (fin ? 1 : 0));
+#define WR(T)                                                                                   \
+  hipLaunchKernelGGL(k_write_w<T>, grid, dim3(256), lds, H->st, static_cast<T*>(Wout), ld, H->n, \
+                     V, KMAX, r, H->small, lam_off, H->dp, H->y, H->y_old, H->dval,             \
+                     sparse ? 1 : 0, rank1 ? 1 : 0, fin ? 1 : 0, f, ts)
+  if (out_prec == PROXSDP_FP32)
+    WR(float);
+  else if (out_prec == PROXSDP_BF16)
+    WR(unsigned short);
+  else
+    WR(double);
+#undef WR
 }
 
-static int lam_slot(int parity) { return SL::LAM + parity * KMAX; }
+// Z = W B for the current iterate through the precision form's dense W
+// (FP32 storage: FP32 MFMA; summed in FP64 by the reduction).
+static void launch_block_lowp(proxsdp_handle* H, const double* B, double* part) {
+  dim3 grid(H->npad / 64, H->ch.nchunks);
+  const float* Wf = static_cast<const float*>(H->Wl);
+  switch (H->k / 16) {
+    case 1: hipLaunchKernelGGL((k_block_partial_f32<1>), grid, dim3(256), 0, H->st, Wf, (int64_t)H->npad, B, H->k, part, H->ch.rows_per_chunk, H->npad); break;
+    case 2: hipLaunchKernelGGL((k_block_partial_f32<2>), grid, dim3(256), 0, H->st, Wf, (int64_t)H->npad, B, H->k, part, H->ch.rows_per_chunk, H->npad); break;
+    case 3: hipLaunchKernelGGL((k_block_partial_f32<3>), grid, dim3(256), 0, H->st, Wf, (int64_t)H->npad, B, H->k, part, H->ch.rows_per_chunk, H->npad); break;
+    default: hipLaunchKernelGGL((k_block_partial_f32<4>), grid, dim3(256), 0, H->st, Wf, (int64_t)H->npad, B, H->k, part, H->ch.rows_per_chunk, H->npad); break;
+  }
+}
+
+// Z = W B applied exactly in FP64 from the factors of the current X, the
+// sparse part D and the rank-one terms (never reads the dense W), with the
+// per-slice Gram partials [B^T B, B^T Z, Z^T Z] for Rayleigh-Ritz.
+static void launch_implicit(proxsdp_handle* H, const double* B, double* Z) {
+  hipStream_t st = H->st;
+  const int pp = 1 - (H->iters & 1);       // factors of the current X
+  const int r = H->iters > 0 ? H->r_old : 0;
+  const int k = H->k;
+  hipLaunchKernelGGL(k_vtb, dim3(H->nsl), dim3(256), 0, st, H->V[pp], r, B, k, H->dp.n_r1,
+                     H->dp.r1_u, H->npad, H->vb_part);
+  const int cnt = (r + H->dp.n_r1) * k;
+  if (cnt > 0)
+    hipLaunchKernelGGL(k_sum_vb, dim3((cnt + 255) / 256), dim3(256), 0, st, H->vb_part, H->nsl, r,
+                       k, H->dp, H->y, lam_slot(pp), H->small);
+  hipLaunchKernelGGL(k_implicit_rows, dim3(H->npad / 4), dim3(256), 0, st, H->dp, H->V[pp], r,
+                     H->small, H->dval, B, k, Z);
+  // Gram partials [B^T B, B^T Z, Z^T Z] per slice (a one-chunk reduction of Z)
+  launch_reduce(Z, 1, nullptr, B, nullptr, H->npad, k, H->gram_part, 0, 0.0, 1.0, true, st);
+}
+
 
 // Reduces the residual partials of the last row-wise call and reads the
 // largest relative Ritz residual of the kept pairs (synchronises).
@@ -712,11 +775,15 @@ static void eig_round(proxsdp_handle* H, int par, bool final_round) {
   const double* Bc = H->B[H->bcur];
   const int nb = (H->bcur + 1) % 3;
   double* Bn = H->B[nb];
-  prof_mark(H, H->ev_pass, H->n_pass, true);
-  launch_block(H->W, H->npad, H->n, H->npad, Bc, H->k, H->part, H->ch, true, st);
-  prof_mark(H, H->ev_pass, H->n_pass, false);
-  launch_reduce(H->part, H->ch.nchunks, H->Z, Bc, nullptr, H->npad, H->k, H->gram_part, 0, 0.0,
-                1.0, true, st);
+  if (H->prec == PROXSDP_FP64) {
+    prof_mark(H, H->ev_pass, H->n_pass, true);
+    launch_block(H->W, H->npad, H->n, H->npad, Bc, H->k, H->part, H->ch, true, st);
+    prof_mark(H, H->ev_pass, H->n_pass, false);
+    launch_reduce(H->part, H->ch.nchunks, H->Z, Bc, nullptr, H->npad, H->k, H->gram_part, 0, 0.0,
+                  1.0, true, st);
+  } else {
+    launch_implicit(H, Bc, H->Z);
+  }
   const double jac_tol = H->opt.eig_strict ? 1e-15 : std::max(1e-15, std::min(1e-6, 0.01 * H->eta));
   launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, jac_tol, st);
   if (final_round)
@@ -740,7 +807,10 @@ static void eig_iteration(proxsdp_handle* H, int par, int m) {
     int nxt = 0;
     while (nxt == cur || nxt == prev) ++nxt;
     prof_mark(H, H->ev_pass, H->n_pass, true);
-    launch_block(H->W, H->npad, H->n, H->npad, H->B[cur], H->k, H->part, H->ch, true, st);
+    if (H->prec == PROXSDP_FP64)
+      launch_block(H->W, H->npad, H->n, H->npad, H->B[cur], H->k, H->part, H->ch, true, st);
+    else
+      launch_block_lowp(H, H->B[cur], H->part);
     prof_mark(H, H->ev_pass, H->n_pass, false);
     launch_reduce(H->part, H->ch.nchunks, H->B[nxt], H->B[cur], prev >= 0 ? H->B[prev] : nullptr,
                   H->npad, H->k, H->gram_part, prev >= 0 ? 2 : 1, 0.0, 1.0, false, st, filt);
@@ -750,11 +820,16 @@ static void eig_iteration(proxsdp_handle* H, int par, int m) {
   }
   int nb = 0;
   while (nb == cur) ++nb;
-  prof_mark(H, H->ev_pass, H->n_pass, true);
-  launch_block(H->W, H->npad, H->n, H->npad, H->B[cur], H->k, H->part, H->ch, true, st);
-  prof_mark(H, H->ev_pass, H->n_pass, false);
-  launch_reduce(H->part, H->ch.nchunks, H->Z, H->B[cur], nullptr, H->npad, H->k, H->gram_part, 0,
-                0.0, 1.0, true, st);
+  if (H->prec == PROXSDP_FP64) {
+    prof_mark(H, H->ev_pass, H->n_pass, true);
+    launch_block(H->W, H->npad, H->n, H->npad, H->B[cur], H->k, H->part, H->ch, true, st);
+    prof_mark(H, H->ev_pass, H->n_pass, false);
+    launch_reduce(H->part, H->ch.nchunks, H->Z, H->B[cur], nullptr, H->npad, H->k, H->gram_part, 0,
+                  0.0, 1.0, true, st);
+  } else {
+    // precision form: the Rayleigh-Ritz pass applies W exactly (FP64 refinement)
+    launch_implicit(H, H->B[cur], H->Z);
+  }
   const double jac_tol = std::max(1e-15, std::min(1e-6, 0.01 * H->eta));
   launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, jac_tol, st);
   launch_rowwise(H, H->B[cur], H->V[par], H->r, H->V[1 - par], H->r_old, H->B[nb], st);
@@ -782,7 +857,8 @@ static void pattern_and_write(proxsdp_handle* H, int par, int ring_slot) {
   f.ring = H->ring;
   f.ring_slot = ring_slot;
   prof_mark(H, H->ev_write, H->n_write, true);
-  launch_write(H, H->W, H->npad, H->V[par], H->r, lam_slot(par), true, true, &f);
+  launch_write(H, H->prec == PROXSDP_FP64 ? (void*)H->W : H->Wl, H->prec, H->npad, H->V[par], H->r,
+               lam_slot(par), true, true, &f);
   prof_mark(H, H->ev_write, H->n_write, false);
 }
 
@@ -882,9 +958,13 @@ static int fill_info(proxsdp_handle* H, const IterRecord& rec, double nonfinite)
 static int confirm_lambda_r(proxsdp_handle* H, double* lam_r) {
   hipStream_t st = H->st;
   const double* Bc = H->B[H->bcur];
-  launch_block(H->W, H->npad, H->n, H->npad, Bc, H->k, H->part, H->ch, true, st);
-  launch_reduce(H->part, H->ch.nchunks, H->Z, Bc, nullptr, H->npad, H->k, H->gram_part, 0, 0.0, 1.0,
-                true, st);
+  if (H->prec == PROXSDP_FP64) {
+    launch_block(H->W, H->npad, H->n, H->npad, Bc, H->k, H->part, H->ch, true, st);
+    launch_reduce(H->part, H->ch.nchunks, H->Z, Bc, nullptr, H->npad, H->k, H->gram_part, 0, 0.0,
+                  1.0, true, st);
+  } else {
+    launch_implicit(H, Bc, H->Z);
+  }
   launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(H->iters & 1), 1, 1e-15, st, 0);
   HIP_OK(hipMemcpyAsync(lam_r, H->small + SL::SC + S_LAMR, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
@@ -970,7 +1050,10 @@ static int warm_start(proxsdp_handle* H) {
 static int init_state(proxsdp_handle* H) {
   hipStream_t st = H->st;
   // state: X0 = 0, y0 = 0
-  zero(H->W, (size_t)H->npad * H->npad, st);
+  if (H->prec == PROXSDP_FP64)
+    zero(H->W, (size_t)H->npad * H->npad, st);
+  else
+    zero(static_cast<double*>(H->Wl), (size_t)H->npad * H->npad * H->wbytes / 8, st);
   zero(H->B[0], (size_t)H->npad * H->k_cap, st);
   zero(H->B[1], (size_t)H->npad * H->k_cap, st);
   zero(H->B[2], (size_t)H->npad * H->k_cap, st);
@@ -1206,7 +1289,7 @@ int proxsdp_get_solution(proxsdp_handle* H, double* X, double* y, int32_t on_dev
     const int par = (H->iters - 1) & 1;
     const int r = H->iters > 0 ? H->r_old : 0;
     if (on_device) {
-      launch_write(H, X, n, H->V[par], r, lam_slot(par), false, false, nullptr);
+      launch_write(H, X, PROXSDP_FP64, n, H->V[par], r, lam_slot(par), false, false, nullptr);
     } else {
       std::vector<double> V((size_t)n * std::max(r, 1)), lam(std::max(r, 1));
       int32_t rr = 0;
@@ -1333,7 +1416,7 @@ int proxsdp_project_psd(const void* S, int32_t n, int64_t lds, int32_t r, int32_
       return fail(PROXSDP_ERR_UNSUPPORTED, "partial eigensolve did not reach tol within the pass budget");
     }
   }
-  if (P) launch_write(&H, static_cast<double*>(P), ldp, H.V[0], re, lam_off, false, false, nullptr);
+  if (P) launch_write(&H, P, PROXSDP_FP64, ldp, H.V[0], re, lam_off, false, false, nullptr);
   std::vector<double> theta(std::max(re, 1));
   HIP_OK(hipMemcpyAsync(theta.data(), H.small + SL::THETA, re * sizeof(double), hipMemcpyDeviceToHost, st));
   if (evecs) {
@@ -1395,14 +1478,14 @@ int proxsdp_profile_totals(proxsdp_handle* H, double* out, int32_t count) {
     HIP_OK(hipEventElapsedTime(&ms, H->ev_pass[2 * i], H->ev_pass[2 * i + 1]));
     v[0] += ms;
     v[2] += 2.0 * np2 * (i < (int)H->prof_k.size() ? H->prof_k[i] : H->k);
-    v[3] += 8.0 * np2;
+    v[3] += (double)H->wbytes * np2;
   }
   for (int i = 0; i < H->n_write; ++i) {
     float ms = 0;
     HIP_OK(hipEventElapsedTime(&ms, H->ev_write[2 * i], H->ev_write[2 * i + 1]));
     v[4] += ms;
     v[6] += 2.0 * pair_cells * (i < (int)H->prof_r.size() ? H->prof_r[i] : H->r);
-    v[7] += 8.0 * n2;
+    v[7] += (double)H->wbytes * n2;
   }
   v[1] = H->n_pass;
   v[5] = H->n_write;

@@ -115,21 +115,19 @@ class Solver:
         return info.to_dict()
 
     def solution(self, on_device: bool = True):
-        """(X, y): X as an n x n float64 tensor (device) or ndarray, y as ndarray."""
+        """(X, y): X as an n x n float64 tensor (device) or ndarray, y as ndarray.
+
+        X is always formed on the device (dense write from the factors) and
+        copied to the host when on_device is False."""
         import torch
         y = np.zeros(self.rows)
-        if on_device:
-            X = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
-            check(lib.proxsdp_get_solution(self._h, C.c_void_p(X.data_ptr()),
-                                           y.ctypes.data_as(C.c_void_p), 0), "get_solution(y)")
-            check(lib.proxsdp_get_solution(self._h, C.c_void_p(X.data_ptr()), None, 1),
-                  "get_solution(X)")
-            torch.cuda.synchronize(self.device)
-            return X, y
-        X = np.zeros((self.n, self.n))
-        check(lib.proxsdp_get_solution(self._h, X.ctypes.data_as(C.c_void_p),
-                                       y.ctypes.data_as(C.c_void_p), 0), "get_solution")
-        return X, y
+        X = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+        check(lib.proxsdp_get_solution(self._h, None, y.ctypes.data_as(C.c_void_p), 0),
+              "get_solution(y)")
+        check(lib.proxsdp_get_solution(self._h, C.c_void_p(X.data_ptr()), None, 1),
+              "get_solution(X)")
+        torch.cuda.synchronize(self.device)
+        return (X, y) if on_device else (X.cpu().numpy(), y)
 
     def factors(self):
         r = C.c_int32()

@@ -188,3 +188,67 @@ def test_solve_trajectory_with_converged_eigensolves(torch_cuda, kind, n, seed):
     X, y = s.solution(on_device=False)
     assert np.abs(X - ref.X).max() <= 1e-6 * max(1.0, np.abs(ref.X).max())
     s.close()
+
+
+# ------------------------------------------------------- precision form
+PREC_FP32 = 1
+
+
+@pytest.mark.parametrize("kind,n,r,K", [("maxcut", 200, 4, 20), ("equip", 180, 3, 20)])
+def test_precision_form_strict_iterates_match_oracle(torch_cuda, kind, n, r, K):
+    """FP32 storage of W with converged eigensolves: every Rayleigh-Ritz pass of
+    the precision form applies W exactly (FP64, from the factors, the sparse part
+    and the rank-one term), so the iterates follow the FP64 oracle."""
+    from paper_1810_05231_amd import Solver
+    _say("precision strict iterates", kind, n, r, K)
+    prob = I.maxcut(n, 0.1, 7) if kind == "maxcut" else I.equipartition(n, 0.1, 7)
+    alpha = 0.95 / O.Operators(prob).norm()
+    s = Solver(prob, r0=r, alpha=alpha, check_every=5, window=1000, eig_strict=1,
+               eig_tol=1e-13, max_iters=K, precision=PREC_FP32)
+    info = s.step(K)
+    Xg, yg = s.solution(on_device=False)
+    Xo, yo, out = _oracle_steps(prob, K, r, alpha)
+    scale = max(1.0, np.abs(Xo).max())
+    _say("  dX", np.abs(Xg - Xo).max() / scale, "dy", np.abs(yg - yo).max())
+    assert info["iters"] == K
+    assert np.abs(Xg - Xo).max() <= 1e-7 * scale
+    assert np.abs(yg - yo).max() <= 1e-7 * max(1.0, np.abs(yo).max())
+    s.close()
+
+
+@pytest.mark.parametrize("kind,n,seed", [("maxcut", 150, 3), ("equip", 120, 4), ("maxcut", 400, 5)])
+def test_precision_form_solve(torch_cuda, kind, n, seed):
+    """FP32 precision form to 1e-4: the oracle's certificate of the answer and
+    the objective against the plain FP64 GPU form (stated error)."""
+    from paper_1810_05231_amd import Solver
+    _say("precision solve", kind, n, seed)
+    prob = I.maxcut(n, 0.05, seed) if kind == "maxcut" else I.equipartition(n, 0.05, seed)
+    s64 = Solver(prob, tol=1e-4)
+    i64 = s64.solve()
+    s32 = Solver(prob, tol=1e-4, precision=PREC_FP32)
+    i32 = s32.solve()
+    _say("  fp64", i64["status_name"], i64["iters"], i64["r"], repr(i64["obj"]))
+    _say("  fp32", i32["status_name"], i32["iters"], i32["r"], repr(i32["obj"]))
+    assert i32["status_name"] == "converged"
+    X, y = s32.solution(on_device=False)
+    cert = O.certificate(prob, X, y)
+    rel = abs(i32["obj"] - i64["obj"]) / abs(i64["obj"])
+    _say("  cert", cert.rho_p, cert.rho_d, cert.rel_gap, "obj rel diff vs fp64", rel)
+    assert max(cert.rho_p, cert.rho_d) <= 2e-4
+    assert cert.lambda_min_X >= -1e-9 * max(1.0, np.abs(X).max())
+    if kind == "maxcut":
+        assert rel <= 1e-4
+    else:
+        X64, y64 = s64.solution(on_device=False)
+        c64 = O.certificate(prob, X64, y64)
+        assert rel <= max(1e-4, 2.0 * max(cert.rel_gap, c64.rel_gap))
+    s64.close()
+    s32.close()
+
+
+def test_precision_bf16_rejected(torch_cuda):
+    from paper_1810_05231_amd import Solver
+    from paper_1810_05231_amd._lib import ProxSDPError
+    prob = I.maxcut(100, 0.1, 0)
+    with pytest.raises(ProxSDPError):
+        Solver(prob, precision=2)
