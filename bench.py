@@ -54,6 +54,11 @@ def main():
     ap.add_argument("--r0", type=int, default=0, help="initial target rank (0 = default, 1)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="storage of W for the timed steps (fp32 = precision form)")
+    ap.add_argument("--serving", type=int, default=0,
+                    help="also run the serving stream with this many requests (0 = skip)")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
+    ap.add_argument("--slots", type=int, default=8, help="serving: solves in flight")
+    ap.add_argument("--budget-gib", type=float, default=32.0, help="serving: HBM budget")
     ap.add_argument("--no-precision-form", action="store_true",
                     help="skip the FP32 precision-form solve reported beside the FP64 result")
     args = ap.parse_args()
@@ -73,6 +78,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.serving_only:
+        out = {"metric": "serving p50/p99 latency (s)", **serving_bench(args, dev)}
+        print(json.dumps(out), flush=True)
+        return
     n = args.n
     t0 = time.perf_counter()
     prob = I.maxcut(n, args.p, args.seed)
@@ -175,6 +184,7 @@ def main():
                          "TFLOPs": round(write_flops / max(write_s, 1e-12) / 1e12, 2)},
         "sweep_share_of_solve": round((pass_s + write_s) / max(sum(times), 1e-9), 3),
     })
+    serving = serving_bench(args, dev) if args.serving else None
     prec = None
     if not args.no_precision_form and not args.iters and args.precision == "fp64":
         prec = precision_form(prob, dev, opts, sum(times) / len(times), last)
@@ -205,10 +215,57 @@ def main():
         },
         "roofline": roofline,
         "precision_form": prec,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     s.close()
+
+
+def serving_bench(args, dev):
+    """Serving stream (precision form): a saturation run with every request
+    present at time 0 gives the throughput; a Poisson stream at 0.7 of that
+    rate gives the p50 / p99 latency (completion - arrival)."""
+    import instances as I
+    from paper_1810_05231_amd.serving import Request, Server, percentile
+    N = args.serving or 512
+    opts = dict(precision=1, tol=args.tol)
+    srv = Server(device=dev, budget_bytes=int(args.budget_gib * (1 << 30)), max_slots=args.slots,
+                 **opts)
+    base = I.serving_stream(N, seed=args.seed, rate=None)
+    log(f"serving: {N} requests, n in [100, 2000], G(n, 8/n), FP32 form, {args.slots} slots")
+    def progress(r, _s):
+        if r.rid % 16 == 0:
+            log(f"  done rid {r.rid} n={r.n} {r.status} iters={r.iters} latency={r.latency:.3f}s")
+
+    t0 = time.perf_counter()
+    res = srv.run([Request(rid, 0.0, p) for rid, _, p in base], on_done=progress)
+    makespan = time.perf_counter() - t0
+    thr = N / makespan
+    ok = sum(r.status == "converged" for r in res)
+    log(f"serving saturation: {makespan:.2f}s, {thr:.2f} solves/s, {ok}/{N} converged")
+    rate = 0.7 * thr
+    stream = I.serving_stream(N, seed=args.seed, rate=rate)
+    t0 = time.perf_counter()
+    res2 = srv.run([Request(rid, a, p) for rid, a, p in stream], on_done=progress)
+    span = time.perf_counter() - t0
+    lat = [r.latency for r in res2]
+    ok2 = sum(r.status == "converged" for r in res2)
+    out = {
+        "workload": f"{N} requests, max-cut/equipartition (fair coin), n ~ U[100, 2000], "
+                    f"G(n, 8/n), FP32 precision form, Poisson arrivals",
+        "slots": args.slots, "budget_GiB": args.budget_gib,
+        "saturated_solves_per_s": round(thr, 3), "saturated_makespan_s": round(makespan, 3),
+        "arrival_rate_per_s": round(rate, 3),
+        "p50_latency_s": round(percentile(lat, 50), 4), "p99_latency_s": round(percentile(lat, 99), 4),
+        "mean_latency_s": round(sum(lat) / len(lat), 4),
+        "solves_per_s": round(N / span, 3), "converged": ok2, "requests": N,
+        "mean_iters": round(sum(r.iters for r in res2) / len(res2), 1),
+        "peak_slots": srv.peak_slots, "peak_bytes": srv.peak_bytes,
+    }
+    log(f"serving stream: p50 {out['p50_latency_s']}s p99 {out['p99_latency_s']}s, "
+        f"{out['solves_per_s']} solves/s, {ok2}/{N} converged")
+    return out
 
 
 def precision_form(prob, dev, opts, t64, info64):

@@ -172,6 +172,17 @@ int proxsdp_step(proxsdp_handle *h, int32_t n_iters, proxsdp_info *info);
  * numerical failure); fills *info (may be NULL).  Synchronises. */
 int proxsdp_solve(proxsdp_handle *h, proxsdp_info *info);
 
+/* Serving form: advances every handle in hs[0 .. count) that is still
+ * running by n_iters PDHG iterations (fewer for a handle that stops).  The
+ * iterations of all handles are enqueued between control checks, each on
+ * its handle's own stream, so that solves of different sizes overlap on the
+ * device; the control checks then synchronise each stream in turn.  Handles
+ * created on the same stream are valid but run one after the other.
+ * infos (host array of count entries, nullable) receives each handle's state.
+ * Synchronises every stream before returning.  Errors: PROXSDP_ERR_INVALID
+ * for a NULL handle array entry or n_iters < 0. */
+int proxsdp_step_many(proxsdp_handle **hs, int32_t count, int32_t n_iters, proxsdp_info *infos);
+
 /* Current iterate: X (n x n, row-major, formed from the rank-r factors) and
  * the dual y (m + p values, unscaled, Section 1.3 sign).  Either pointer may
  * be NULL.  on_device = 0: host pointers; 1: device pointers.  Synchronises. */

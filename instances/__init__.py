@@ -311,3 +311,28 @@ def lowrank_plus_negative_spectrum(n: int, r_pos: int, seed: int, top: float = 1
     pos = gap + (top - gap) * rng.random(r_pos)
     rest = -neg * rng.random(n - r_pos)
     return np.concatenate([pos, rest])
+
+
+def serving_stream(count: int, seed: int = 0, n_lo: int = 100, n_hi: int = 2000,
+                   mean_degree: float = 8.0, rate: float | None = None):
+    """The serving workload: `count` requests, request i is max-cut or
+    equipartition (one fair coin) on G(n, mean_degree / n) with n uniform in
+    {n_lo .. n_hi}, graph seed = i.  Arrivals form a Poisson process of the
+    given rate (requests per second; None = all at time 0).
+
+    Returns a list of (request id, arrival time in s, Problem).
+    """
+    rng = np.random.default_rng(seed)
+    kinds = rng.integers(0, 2, size=count)
+    sizes = rng.integers(n_lo, n_hi + 1, size=count)
+    if rate is None:
+        arrivals = np.zeros(count)
+    else:
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    out = []
+    for i in range(count):
+        n = int(sizes[i])
+        p_edge = min(1.0, mean_degree / n)
+        prob = maxcut(n, p_edge, i) if kinds[i] == 0 else equipartition(n, p_edge, i)
+        out.append((i, float(arrivals[i]), prob))
+    return out

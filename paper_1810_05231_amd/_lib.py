@@ -96,6 +96,7 @@ def _load():
         "proxsdp_profile_enable": (C.c_int, [H, C.c_int32]),
         "proxsdp_profile_read": (C.c_int, [H, _f64p, _i32p, _f64p, _i32p]),
         "proxsdp_profile_totals": (C.c_int, [H, _f64p, C.c_int32]),
+        "proxsdp_step_many": (C.c_int, [C.POINTER(H), C.c_int32, C.c_int32, C.c_void_p]),
         "proxsdp_debug_scalars": (C.c_int, [H, _f64p, C.c_int32]),
         "proxsdp_rank_path": (C.c_int, [H, _i32p, _i32p, _i32p, C.c_int32, _i32p]),
         "proxsdp_last_error": (C.c_char_p, []),

@@ -1234,6 +1234,72 @@ int proxsdp_step(proxsdp_handle* H, int32_t n_iters, proxsdp_info* info) {
   return PROXSDP_OK;
 }
 
+int proxsdp_step_many(proxsdp_handle** hs, int32_t count, int32_t n_iters, proxsdp_info* infos) {
+  g_err.clear();
+  if (count < 0 || (count > 0 && !hs)) return fail(PROXSDP_ERR_INVALID, "bad handle array");
+  if (n_iters < 0) return fail(PROXSDP_ERR_INVALID, "n_iters < 0");
+  for (int i = 0; i < count; ++i)
+    if (!hs[i]) return fail(PROXSDP_ERR_INVALID, "handle " + std::to_string(i) + " is NULL");
+  auto t_last = std::chrono::steady_clock::now();
+  int remaining = n_iters;
+  while (remaining > 0) {
+    // enqueue up to the next control check of every running handle (each on
+    // its own stream, so that their kernels overlap on the device) ...
+    int chunk = remaining;
+    bool any = false;
+    for (int i = 0; i < count; ++i) {
+      proxsdp_handle* H = hs[i];
+      if (H->status != PROXSDP_STATUS_RUNNING) continue;
+      const int to_check = H->opt.check_every - H->iters % H->opt.check_every;
+      chunk = std::min(chunk, to_check);
+      any = true;
+    }
+    if (!any) break;
+    for (int i = 0; i < count; ++i) {
+      proxsdp_handle* H = hs[i];
+      if (H->status != PROXSDP_STATUS_RUNNING) continue;
+      for (int t = 0; t < chunk; ++t) iterate_once(H);
+    }
+    // ... then the checks, in handle order (each synchronises its own stream)
+    for (int i = 0; i < count; ++i) {
+      proxsdp_handle* H = hs[i];
+      if (H->status != PROXSDP_STATUS_RUNNING) continue;
+      if (H->iters % H->opt.check_every == 0) {
+        const int rc = control(H);
+        if (rc) return rc;
+        const auto t = std::chrono::steady_clock::now();
+        H->time_s += std::chrono::duration<double>(t - t_last).count();
+        if (H->status == PROXSDP_STATUS_RUNNING && H->iters >= H->opt.max_iters)
+          H->status = PROXSDP_STATUS_MAX_ITERS;
+        if (H->status == PROXSDP_STATUS_RUNNING && H->opt.time_limit_s > 0 &&
+            H->time_s > H->opt.time_limit_s)
+          H->status = PROXSDP_STATUS_TIME_LIMIT;
+        H->last.status = H->status;
+        H->last.time_s = H->time_s;
+      }
+    }
+    t_last = std::chrono::steady_clock::now();
+    remaining -= chunk;
+  }
+  for (int i = 0; i < count; ++i) {
+    proxsdp_handle* H = hs[i];
+    HIP_OK(hipStreamSynchronize(H->st));
+    if (infos) {
+      if (H->iters > 0 && H->iters % H->opt.check_every != 0) {
+        std::vector<IterRecord> recs;
+        const int rc = read_records(H, H->iters - 1, 1, recs);
+        if (rc) return rc;
+        HIP_OK(hipStreamSynchronize(H->st));
+        fill_info(H, recs.back(), 0.0);
+      }
+      H->last.status = H->status;
+      H->last.time_s = H->time_s;
+      infos[i] = H->last;
+    }
+  }
+  return PROXSDP_OK;
+}
+
 int proxsdp_solve(proxsdp_handle* H, proxsdp_info* info) {
   g_err.clear();
   if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");

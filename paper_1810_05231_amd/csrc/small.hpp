@@ -48,12 +48,13 @@ __device__ __forceinline__ int jacobi_eig(double* A, int lda, double* U, int ldu
   int* pp = reinterpret_cast<int*>(cs + 2 * np);
   int* qq = pp + np;
   int sweeps = 0;
-  __shared__ double offd[2];
+  __shared__ double offw[2 * 16];   // per-wave partial sums (fixed-order reduction)
   __shared__ int anyrot[2];
   if (tid == 0) { anyrot[0] = 1; anyrot[1] = 1; }
+  const int nw = nt >> 6;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     // convergence test on the off-diagonal mass
-    if (tid == 0) { offd[0] = 0.0; offd[1] = 0.0; *flag = 0; }
+    if (tid == 0) *flag = 0;
     __syncthreads();
     double off = 0.0, dg = 0.0;
     for (int t = tid; t < (k << 6); t += nt) {
@@ -68,12 +69,18 @@ __device__ __forceinline__ int jacobi_eig(double* A, int lda, double* U, int ldu
       dg += __shfl_xor(dg, o);
     }
     if ((tid & 63) == 0) {
-      atomicAdd(&offd[0], off);
-      atomicAdd(&offd[1], dg);
+      offw[2 * (tid >> 6)] = off;
+      offw[2 * (tid >> 6) + 1] = dg;
     }
     __syncthreads();
-    if (!(offd[0] > tol_off * tol_off * offd[1]) || !(offd[0] > 1e-300)) break;
-    const double pair_thr = threshold ? tol_off * sqrt(offd[1]) / k : 0.0;
+    off = 0.0;
+    dg = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      off += offw[2 * w];
+      dg += offw[2 * w + 1];
+    }
+    if (!(off > tol_off * tol_off * dg) || !(off > 1e-300)) break;
+    const double pair_thr = threshold ? tol_off * sqrt(dg) / k : 0.0;
     for (int rnd = 0; rnd < kk - 1; ++rnd) {
       if (threshold && tid == 0) anyrot[(rnd + 1) & 1] = 0;
       for (int i = tid; i < np; i += nt) {

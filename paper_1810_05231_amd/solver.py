@@ -12,7 +12,7 @@ import numpy as np
 from . import _lib
 from ._lib import FP64, Info, Problem, check, default_options, lib
 
-__all__ = ["Solver", "project_psd", "problem_struct", "workspace_size"]
+__all__ = ["Solver", "project_psd", "problem_struct", "workspace_size", "step_many"]
 
 
 def _ptr(a: np.ndarray, ctype):
@@ -87,7 +87,9 @@ class Solver:
     ``proxsdp_options``.
     """
 
-    def __init__(self, prob, device="cuda", **options):
+    def __init__(self, prob, device="cuda", stream=None, **options):
+        """`stream`: a torch.cuda.Stream the handle runs on (default: the
+        current stream); the workspace is allocated on it."""
         import torch
         self.device = torch.device(device)
         self.n = int(prob.n)
@@ -98,10 +100,13 @@ class Solver:
         check(lib.proxsdp_workspace_size(C.byref(s), C.byref(o), C.byref(nb)),
               "proxsdp_workspace_size")
         self.ws_bytes = int(nb.value)
-        self._buf, ptr = _device_buffer(self.ws_bytes, self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.stream(self.stream):
+            self._buf, ptr = _device_buffer(self.ws_bytes, self.device)
         self._h = C.c_void_p()
         check(lib.proxsdp_create(C.byref(s), C.byref(o), C.c_void_p(ptr), self.ws_bytes,
-                                 _stream_handle(self.device), C.byref(self._h)), "proxsdp_create")
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(self._h)),
+              "proxsdp_create")
         del keep
 
     def step(self, n_iters: int = 1) -> dict:
@@ -173,6 +178,20 @@ class Solver:
         if getattr(self, "_h", None) is not None and self._h.value:
             lib.proxsdp_destroy(self._h)
             self._h = C.c_void_p()
+        self._buf = None
+
+
+def step_many(solvers, n_iters: int):
+    """Advances several solvers (each on its own stream) by n_iters iterations
+    with their kernels interleaved on the device; returns their info dicts."""
+    cnt = len(solvers)
+    if cnt == 0:
+        return []
+    hs = (C.c_void_p * cnt)(*[s._h.value for s in solvers])
+    infos = (Info * cnt)()
+    check(lib.proxsdp_step_many(hs, cnt, int(n_iters), C.cast(infos, C.c_void_p)),
+          "proxsdp_step_many")
+    return [infos[i].to_dict() for i in range(cnt)]
 
     def __del__(self):
         try:
