@@ -54,6 +54,13 @@ def main():
     ap.add_argument("--r0", type=int, default=0, help="initial target rank (0 = default, 1)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="storage of W for the timed steps (fp32 = precision form)")
+    ap.add_argument("--workload", choices=["maxcut", "equip", "snl"], default="maxcut",
+                    help="maxcut / equip: G(n, p); snl: --n sensors (2000 for the full case)")
+    ap.add_argument("--progress", type=int, default=0,
+                    help="solve in chunks of this many iterations with a progress line each")
+    ap.add_argument("--time-limit", type=float, default=0.0, help="solver time limit (s)")
+    ap.add_argument("--snl-noise", type=float, default=0.0,
+                    help="snl: multiplicative distance noise (0 = exact distances, as in Section 5.2)")
     ap.add_argument("--serving", type=int, default=0,
                     help="also run the serving stream with this many requests (0 = skip)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
@@ -84,8 +91,13 @@ def main():
         return
     n = args.n
     t0 = time.perf_counter()
-    prob = I.maxcut(n, args.p, args.seed)
-    log(f"instance {prob.name}: n={n} edges={prob.meta['edges']} ({time.perf_counter()-t0:.1f}s)")
+    if args.workload == "maxcut":
+        prob = I.maxcut(n, args.p, args.seed)
+    elif args.workload == "equip":
+        prob = I.equipartition(n, args.p, args.seed)
+    else:
+        prob = I.snl(n, args.seed, noise=args.snl_noise)
+    log(f"instance {prob.name}: n={prob.n} m={prob.m} p={prob.p} ({time.perf_counter()-t0:.1f}s)")
     t0 = time.perf_counter()
     opts = dict(tol=args.tol)
     if args.window:
@@ -94,6 +106,8 @@ def main():
         opts["eig_rel"] = args.eig_rel
     if args.r0:
         opts["r0"] = args.r0
+    if args.time_limit:
+        opts["time_limit_s"] = args.time_limit
     main_opts = dict(opts)
     if args.precision == "fp32":
         main_opts["precision"] = 1
@@ -117,7 +131,16 @@ def main():
         check(lib.proxsdp_reset(s._h), "proxsdp_reset")
         if profile:
             check(lib.proxsdp_profile_enable(s._h, 1), "profile_enable")
-        info = s.step(args.iters) if args.iters else s.solve()
+        if args.iters:
+            info = s.step(args.iters)
+        elif args.progress:
+            info = s.step(args.progress)
+            while info["status_name"] == "running":
+                log(f"  ... iters={info['iters']} r={info['r']} rho=({info['rho_p']:.2e},"
+                    f"{info['rho_d']:.2e}) time={info['time_s']:.1f}s")
+                info = s.step(args.progress)
+        else:
+            info = s.solve()
         prof = None
         if profile:
             tot = np.zeros(8)
@@ -168,7 +191,7 @@ def main():
     roofline = dict(roof)
     roofline.update({
         "traffic": (PASS_K64_TRAFFIC_BYTES["read"] + PASS_K64_TRAFFIC_BYTES["write"]
-                    if n == 5000 else None),
+                    if (n == 5000 and args.workload == "maxcut" and args.precision == "fp64") else None),
         "traffic_note": "HBM bytes per k=64 launch (read 227.8 MB + write 31.1 MB, rocprofv3 "
                         "FETCH_SIZE/WRITE_SIZE, copy-calibrated) vs 204.5 MB algorithmic read",
         "kernel": "k_block_partial_f64 (dense pass W B, FP64 MFMA)",
@@ -202,11 +225,13 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded Erdos-Renyi graph, unit weights)",
+        "dtype": "f64" if args.precision == "fp64" else "f32 W / f64 Rayleigh-Ritz",
+        "data": "synthetic (seeded; Erdos-Renyi graphs with unit weights, or random sensor networks)",
         "config": {
-            "workload": f"maxcut G({n},{args.p}) seed {args.seed}, plain FP64 LR-PD-SDP to 1e-4",
-            "n": n, "edges": int(prob.meta["edges"]), "tol": args.tol,
+            "workload": (f"{args.workload} G({n},{args.p}) seed {args.seed}" if args.workload != "snl"
+                         else f"sensor localisation, {n} sensors, seed {args.seed}, noise {args.snl_noise}")
+                        + f", {args.precision.upper()} LR-PD-SDP to {args.tol:g}",
+            "n": int(prob.n), "m": int(prob.m), "p": int(prob.p), "tol": args.tol,
             "iters": last["iters"], "final_rank": last["r"], "passes": last["passes"],
             "obj": last["obj"], "rho_p": last["rho_p"], "rho_d": last["rho_d"],
             "setup_s": round(setup_s, 3), "rank_path": s.rank_path(), "rank_X": rank_x,

@@ -119,8 +119,10 @@ typedef struct {
   int32_t eig_strict;   /* 1: every iteration repeats eigensolver rounds until the
                            kept Ritz pairs meet eig_tol (synchronises per round;
                            for verification), 0 (default): adaptive schedule    */
-  double eig_rel;       /* adaptive schedule: target relative Ritz residual
-                           max(eig_tol, eig_rel * max(rho_p, rho_d)) (default 0.2) */
+  double eig_rel;       /* adaptive schedule: the absolute Ritz residual of the
+                           kept pairs is held below max(eig_tol * max|theta|,
+                           eig_rel * alpha * eps_p), a fraction of the current
+                           primal step (default 0.2)                              */
 } proxsdp_options;
 
 /* ------------------------------------------------------------- info */

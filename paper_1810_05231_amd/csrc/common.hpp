@@ -71,7 +71,7 @@ enum Scalar {
 // One record per iteration (written by the finalising workgroup).
 struct IterRecord {
   double eps_p, eps_d, obj, dual_obj;
-  double lambda_r, lambda_r1, maxres, gersh;
+  double lambda_r, lambda_r1, maxres, normw;   // maxres relative to normw = max |theta|
 };
 
 // Device views of the preprocessed problem.

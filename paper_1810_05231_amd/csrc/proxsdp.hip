@@ -880,7 +880,15 @@ static void iterate_once(proxsdp_handle* H) {
     }
     eig_round(H, par, true);
   } else {
-    eig_iteration(H, par, H->m_rounds);
+    if (H->m_rounds <= 2) {
+      eig_iteration(H, par, H->m_rounds);
+    } else {
+      // higher filter degrees without re-orthogonalisation collapse the basis
+      // onto the dominant eigenvectors when the spectrum is wide: take the
+      // extra passes as full rounds (pass, Rayleigh-Ritz, next basis)
+      for (int rd = 0; rd < H->m_rounds - 2; ++rd) eig_round(H, par, false);
+      eig_iteration(H, par, 2);
+    }
   }
   // dual step
   hipLaunchKernelGGL(k_gather_dual, dim3(H->nrow_blocks), dim3(256), 0, st, H->dp, H->V[par],
@@ -950,25 +958,37 @@ static int fill_info(proxsdp_handle* H, const IterRecord& rec, double nonfinite)
   return PROXSDP_OK;
 }
 
-// lambda_r of the current W from one dense pass and a Rayleigh-Ritz step on
-// the Cholesky path (every Ritz value resolved).  The Newton path of the
-// small eigensolver leaves the non-positive unwanted tail unresolved, so the
-// rank test confirms a passing lambda_r this way before the solve stops.
-// Overwrites only data the next iteration recomputes.
+// lambda_r of the current W for the rank test, from a converged subspace:
+// eight filtered eigensolver rounds (dense pass or exact apply, Rayleigh-Ritz,
+// next basis), the last one on the Cholesky path (every Ritz value resolved;
+// the Newton path leaves the non-positive tail unresolved).  A single round
+// on the iteration's basis can underestimate lambda_r (Ritz values interlace
+// from below) when a dense cluster of small eigenvalues has not converged.
+// Overwrites only data the next iteration recomputes (and improves the basis).
 static int confirm_lambda_r(proxsdp_handle* H, double* lam_r) {
   hipStream_t st = H->st;
-  const double* Bc = H->B[H->bcur];
-  if (H->prec == PROXSDP_FP64) {
-    launch_block(H->W, H->npad, H->n, H->npad, Bc, H->k, H->part, H->ch, true, st);
-    launch_reduce(H->part, H->ch.nchunks, H->Z, Bc, nullptr, H->npad, H->k, H->gram_part, 0, 0.0,
-                  1.0, true, st);
-  } else {
-    launch_implicit(H, Bc, H->Z);
+  const int slot = H->iters & 1;   // lambda slot the next iteration overwrites
+  const int rounds = 8;
+  for (int rd = 0; rd < rounds; ++rd) {
+    const double* Bc = H->B[H->bcur];
+    if (H->prec == PROXSDP_FP64) {
+      launch_block(H->W, H->npad, H->n, H->npad, Bc, H->k, H->part, H->ch, true, st);
+      launch_reduce(H->part, H->ch.nchunks, H->Z, Bc, nullptr, H->npad, H->k, H->gram_part, 0, 0.0,
+                    1.0, true, st);
+    } else {
+      launch_implicit(H, Bc, H->Z);
+    }
+    launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(slot), 1, 1e-15, st,
+              rd == rounds - 1 ? 0 : 10);
+    if (rd < rounds - 1) {
+      const int nb = (H->bcur + 1) % 3;
+      launch_rowwise(H, Bc, nullptr, H->r, nullptr, 0, H->B[nb], st);
+      H->bcur = nb;
+    }
+    H->passes += 1;
   }
-  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(H->iters & 1), 1, 1e-15, st, 0);
   HIP_OK(hipMemcpyAsync(lam_r, H->small + SL::SC + S_LAMR, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  H->passes += 1;
   return PROXSDP_OK;
 }
 
@@ -1014,15 +1034,24 @@ static int control(proxsdp_handle* H) {
       H->hist.clear();
     }
   }
-  // accuracy schedule of the partial eigensolve: relative Ritz residual target
-  // tied to the current residual level (summable errors, Section 3.2)
+  // accuracy schedule of the partial eigensolve (summable errors, Section
+  // 3.2): an eigen error delta in X moves eps_p by about delta / alpha, so the
+  // absolute Ritz residual of the kept pairs is held below
+  //   eig_rel * alpha * eps_p   (floor: eig_tol * max|theta|),
+  // i.e. a fixed fraction of the current primal step.  The target is tied to
+  // the iteration's own scale, not to ||W|| (a target relative to ||W|| is
+  // far too loose for problems with C = 0, such as sensor localisation).
   if (!H->full) {
-    const double eta = std::max(H->opt.eig_tol, H->opt.eig_rel * std::max(rho_p, rho_d));
-    H->eta = eta;
-    double worst = 0;
-    for (auto& x : recs) worst = std::max(worst, x.maxres);
-    if (worst > eta && H->m_rounds < H->opt.max_passes) H->m_rounds += 1;
-    else if (worst < 0.05 * eta && H->m_rounds > 1) H->m_rounds -= 1;
+    double worst = 0, normw = 0;
+    for (auto& x : recs) {
+      worst = std::max(worst, x.maxres * x.normw);
+      normw = std::max(normw, x.normw);
+    }
+    const double eta_abs =
+        std::max(H->opt.eig_tol * normw, H->opt.eig_rel * H->opt.alpha * rec.eps_p);
+    H->eta = normw > 0 ? eta_abs / normw : H->opt.eig_tol;
+    if (worst > eta_abs && H->m_rounds < H->opt.max_passes) H->m_rounds += 1;
+    else if (worst < 0.05 * eta_abs && H->m_rounds > 1) H->m_rounds -= 1;
   }
   fill_info(H, rec, nonfinite);
   return PROXSDP_OK;

@@ -620,6 +620,14 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
     if (!(lo < thk)) lo = thk - 0.5 * (vals[0] - thk) - 1e-300;
     fc = 0.5 * (lo + thk);
     fe = fmax(0.5 * (thk - lo), 1e-300);
+    // A spectrum of zero width (e.g. W = 0 before the first step of a problem
+    // with C = 0) gives no direction to amplify, and the predicted norms
+    // below would underflow: use the neutral filter W + I, which keeps the
+    // basis (and is harmless for the Chebyshev passes).
+    if (!(vals[0] - lo > 1e-200)) {
+      fc = -1.0;
+      fe = 1.0;
+    }
   }
   const double gam = filter ? fmax(fabs(vals[0] - fc), fe) : scale;
   for (int c = tid; c < k; c += nt) {

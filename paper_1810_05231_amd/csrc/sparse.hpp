@@ -284,7 +284,7 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     rec.lambda_r = sc[S_LAMR];
     rec.lambda_r1 = sc[S_LAMR1];
     rec.maxres = sc[S_MAXRES];
-    rec.gersh = lo + gamma_lo;
+    rec.normw = sc[S_NORMW];
     f.ring[f.ring_slot] = rec;
   }
 }
