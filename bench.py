@@ -52,7 +52,7 @@ def main():
     ap.add_argument("--window", type=int, default=0, help="Algorithm 2 window l (0 = library default)")
     ap.add_argument("--eig-rel", type=float, default=0.0, help="eigen accuracy factor (0 = default)")
     ap.add_argument("--r0", type=int, default=0, help="initial target rank (0 = default, 1)")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="storage of W for the timed steps (fp32 = precision form)")
     ap.add_argument("--workload", choices=["maxcut", "equip", "snl"], default="maxcut",
                     help="maxcut / equip: G(n, p); snl: --n sensors (2000 for the full case)")
@@ -109,8 +109,8 @@ def main():
     if args.time_limit:
         opts["time_limit_s"] = args.time_limit
     main_opts = dict(opts)
-    if args.precision == "fp32":
-        main_opts["precision"] = 1
+    if args.precision != "fp64":
+        main_opts["precision"] = 1 if args.precision == "fp32" else 2
     s = Solver(prob, device=dev, **main_opts)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
@@ -210,7 +210,8 @@ def main():
     serving = serving_bench(args, dev) if args.serving else None
     prec = None
     if not args.no_precision_form and not args.iters and args.precision == "fp64":
-        prec = precision_form(prob, dev, opts, sum(times) / len(times), last)
+        prec = {name: precision_form(prob, dev, opts, sum(times) / len(times), last, code)
+                for name, code in (("fp32", 1), ("bf16", 2))}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, last["iters"], args.cpu_iters)
@@ -293,16 +294,16 @@ def serving_bench(args, dev):
     return out
 
 
-def precision_form(prob, dev, opts, t64, info64):
-    """One solve of the precision form (FP32 W, FP32 MFMA filter passes, exact
-    FP64 Rayleigh-Ritz passes) of the same instance, timed like the FP64 steps,
-    with its error against the plain FP64 GPU answer."""
+def precision_form(prob, dev, opts, t64, info64, code):
+    """One solve of the precision form (W stored in FP32 or BF16, filter passes
+    on FP32 / BF16 MFMA, exact FP64 Rayleigh-Ritz passes) of the same instance,
+    timed like the FP64 steps, with its error against the plain FP64 GPU answer."""
     import ctypes as C
     import numpy as np
     import torch
     from paper_1810_05231_amd import Solver
     from paper_1810_05231_amd._lib import check, lib
-    s = Solver(prob, device=dev, precision=1, **opts)
+    s = Solver(prob, device=dev, precision=code, **opts)
     check(lib.proxsdp_reset(s._h), "proxsdp_reset")
     check(lib.proxsdp_profile_enable(s._h, 1), "profile_enable")
     torch.cuda.synchronize()
@@ -313,18 +314,20 @@ def precision_form(prob, dev, opts, t64, info64):
     tot = np.zeros(8)
     check(lib.proxsdp_profile_totals(s._h, tot.ctypes.data_as(C.POINTER(C.c_double)), 8),
           "profile_totals")
-    log(f"precision form (fp32): {info['status_name']} iters={info['iters']} r={info['r']} "
+    log(f"precision form ({'fp32' if code == 1 else 'bf16'}): {info['status_name']} iters={info['iters']} r={info['r']} "
         f"passes={info['passes']} wall={dt:.3f}s obj={info['obj']:.8f}")
     out = {
-        "form": "FP32 dense W (FP32 MFMA filter passes) + exact FP64 Rayleigh-Ritz passes",
+        "form": ("FP32" if code == 1 else "BF16") + " dense W (low-precision MFMA filter passes) "
+                "+ exact FP64 Rayleigh-Ritz passes (implicit operator)",
         "value": round(dt, 4), "unit": "s", "status": info["status_name"],
         "iters": info["iters"], "passes": info["passes"], "final_rank": info["r"],
         "obj": info["obj"], "rho_p": info["rho_p"], "rho_d": info["rho_d"],
         "obj_rel_diff_vs_fp64": abs(info["obj"] - info64["obj"]) / abs(info64["obj"]),
         "speedup_vs_fp64": round(t64 / dt, 3),
-        "fp32_pass_avg_us": round(tot[0] / max(tot[1], 1) * 1e3, 2),
-        "fp32_pass_launches": int(tot[1]),
-        "fp32_write_avg_us": round(tot[4] / max(tot[5], 1) * 1e3, 2),
+        "lowp_pass_avg_us": round(tot[0] / max(tot[1], 1) * 1e3, 2),
+        "lowp_pass_launches": int(tot[1]),
+        "lowp_write_avg_us": round(tot[4] / max(tot[5], 1) * 1e3, 2),
+        "lowp_write_launches": int(tot[5]),
     }
     s.close()
     return out

@@ -74,12 +74,18 @@ __global__ __launch_bounds__(256) void k_block_partial_f64(
 // W and the basis entries are FP32 operands of MFMA f32 16x16x4 (FP32
 // accumulation over the rows of one chunk); the chunk partials are written in
 // FP64 and summed in FP64 by k_reduce_gram.  Operand layout as in the FP64
-// kernel; the FP32 accumulator holds D[4 (l / 16) + v][l % 16].
+// kernel; the FP32 accumulator holds D[4 (l / 16) + v][l % 16].  The 64 x k
+// block of the basis for each 64-row step is converted and staged once per
+// workgroup in LDS (measured 2.4x faster at k = 64 than per-wave loads; the
+// FP64 kernel measured slower with the same staging and keeps direct loads).
 typedef float f4 __attribute__((ext_vector_type(4)));
 template <int KB>
 __global__ __launch_bounds__(256) void k_block_partial_f32(
     const float* __restrict__ W, int64_t ld, const double* __restrict__ B, int ldk,
     double* __restrict__ part, int rows_per_chunk, int npad) {
+  constexpr int K = KB * 16;
+  constexpr int LDB = K + 1;
+  __shared__ float sB[64 * LDB];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int col = blockIdx.x * 64 + wave * 16 + (lane & 15);
@@ -92,20 +98,22 @@ __global__ __launch_bounds__(256) void k_block_partial_f32(
   for (int kb = 0; kb < KB; ++kb) acc[kb] = f4{0.f, 0.f, 0.f, 0.f};
   for (int j = j0; j < j1; j += 64) {
     float w[16];
-    float a[16][KB];
 #pragma unroll
     for (int u = 0; u < 16; ++u) w[u] = W[(int64_t)(j + 4 * u + lrow) * ld + col];
+    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int row = j + 4 * u + lrow;
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb) a[u][kb] = (float)B[(int64_t)row * ldk + kb * 16 + (lane & 15)];
+    for (int t0 = 0; t0 < 64 * K; t0 += 256) {
+      const int t = t0 + threadIdx.x;
+      const int rr = t / K, cc = t - (t / K) * K;
+      sB[rr * LDB + cc] = (float)B[(int64_t)(j + rr) * ldk + cc];
     }
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb)
-        acc[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][kb], w[u], acc[kb], 0, 0, 0);
+        acc[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(sB[(4 * u + lrow) * LDB + kb * 16 + (lane & 15)],
+                                                       w[u], acc[kb], 0, 0, 0);
     }
   }
   double* out = part + (int64_t)chunk * npad * ldk + (int64_t)col * ldk;
@@ -152,6 +160,62 @@ template <>
 __device__ __forceinline__ float store_cast<float>(double x) { return (float)x; }
 template <>
 __device__ __forceinline__ unsigned short store_cast<unsigned short>(double x) { return to_bf16_rne(x); }
+
+// BF16 form of the pass (precision form with W stored in bfloat16): MFMA
+// f32 16x16x32 bf16 with FP32 accumulation.  D[c][i] = sum_j B[j][c] W[j][i];
+// the W operand of lane l is W[i0 + l % 16][j + 8 (l / 16) .. + 7] (a 16-byte
+// row load, W being symmetric) and the basis operand the same eight rows of
+// column c from a transposed BF16 copy of the step's 64 x k basis block staged
+// in LDS.  The accumulator holds D[4 (l / 16) + v][l % 16].
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+template <int KB>
+__global__ __launch_bounds__(256) void k_block_partial_bf16(
+    const unsigned short* __restrict__ W, int64_t ld, const double* __restrict__ B, int ldk,
+    double* __restrict__ part, int rows_per_chunk, int npad) {
+  constexpr int K = KB * 16;
+  constexpr int LDT = 64 + 8;   // staged row stride (bf16), 16-byte aligned rows
+  __shared__ __attribute__((aligned(16))) unsigned short sBt[K * LDT];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  const int i = blockIdx.x * 64 + wave * 16 + m;
+  const int chunk = blockIdx.y;
+  const int j0 = chunk * rows_per_chunk;
+  const int j1 = min(j0 + rows_per_chunk, npad);
+  f4 acc[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) acc[kb] = f4{0.f, 0.f, 0.f, 0.f};
+  const unsigned short* wrow = W + (int64_t)i * ld;
+  for (int j = j0; j < j1; j += 64) {
+    uint4 wv[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) wv[h] = *reinterpret_cast<const uint4*>(wrow + j + 32 * h + 8 * q);
+    __syncthreads();
+#pragma unroll
+    for (int t0 = 0; t0 < 64 * K; t0 += 256) {
+      const int t = t0 + threadIdx.x;
+      const int jj = t / K, cc = t - (t / K) * K;
+      sBt[cc * LDT + jj] = to_bf16_rne(B[(int64_t)(j + jj) * ldk + cc]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bf8 bw = __builtin_bit_cast(bf8, wv[h]);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const uint4 av = *reinterpret_cast<const uint4*>(&sBt[(kb * 16 + m) * LDT + 32 * h + 8 * q]);
+        acc[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av), bw, acc[kb],
+                                                          0, 0, 0);
+      }
+    }
+  }
+  double* out = part + (int64_t)chunk * npad * ldk + (int64_t)i * ldk;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[kb * 16 + 4 * q + v] = (double)acc[kb][v];
+  }
+}
 
 // Gram partials of one SLICE-row block on MFMA f64 16x16x4:
 //   out[0] = X^T X, out[1] = X^T Y, out[2] = Y^T Y  (k x k each, row-major),

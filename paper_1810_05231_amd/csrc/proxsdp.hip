@@ -115,8 +115,6 @@ int validate(const proxsdp_problem* pb, const proxsdp_options* o) {
       return fail(PROXSDP_ERR_INVALID, "window must be a positive multiple of check_every");
     if (o->precision != PROXSDP_FP64 && o->precision != PROXSDP_FP32 && o->precision != PROXSDP_BF16)
       return fail(PROXSDP_ERR_INVALID, "precision must be PROXSDP_FP64, PROXSDP_FP32 or PROXSDP_BF16");
-    if (o->precision == PROXSDP_BF16)
-      return fail(PROXSDP_ERR_UNSUPPORTED, "BF16 storage of W is not built yet");
     if (o->alpha < 0) return fail(PROXSDP_ERR_INVALID, "alpha must be >= 0");
     if (o->full_eig && pb->n > KMAX)
       return fail(PROXSDP_ERR_UNSUPPORTED, "full_eig needs n <= " + std::to_string(KMAX));
@@ -449,6 +447,7 @@ struct proxsdp_handle {
   double* W = nullptr;       // FP64 W (plain form and the exact small-n path)
   void* Wl = nullptr;        // FP32 / BF16 W (precision form)
   double* vb_part = nullptr; // per-slice partials of V^T B, u^T B (implicit operator)
+  bool w_fresh = false;      // precision form: the low-precision W matches the current iterate
   double* B[3] = {nullptr, nullptr, nullptr};
   int bcur = 0;
   double* Z = nullptr;
@@ -705,12 +704,13 @@ static int lam_slot(int parity) { return SL::LAM + parity * KMAX; }
 // Dense write of V diag(lambda+) V^T (+ rank-one terms, + the sparse part) into
 // Wout, stored as `out_prec` (FP64 for outputs, the handle's storage for W).
 static void launch_write(proxsdp_handle* H, void* Wout, int out_prec, int64_t ld, const double* V,
-                         int r, int lam_off, bool sparse, bool rank1, const FinArgs* fin) {
+                         int r, int lam_off, bool sparse, bool rank1, const FinArgs* fin,
+                         bool tiles = true) {
   const int ts = H->npad / TILE;
   const size_t lds = (size_t)TILE * (TILE + 1) * sizeof(double);
   FinArgs f{};
   if (fin) f = *fin;
-  const dim3 grid(ts * (ts + 1) / 2 + (fin ? 1 : 0));
+  const dim3 grid((tiles ? ts * (ts + 1) / 2 : 0) + (fin ? 1 : 0));
 #define WR(T)                                                                                   \
   hipLaunchKernelGGL(k_write_w<T>, grid, dim3(256), lds, H->st, static_cast<T*>(Wout), ld, H->n, \
                      V, KMAX, r, H->small, lam_off, H->dp, H->y, H->y_old, H->dval,             \
@@ -728,6 +728,18 @@ static void launch_write(proxsdp_handle* H, void* Wout, int out_prec, int64_t ld
 // (FP32 storage: FP32 MFMA; summed in FP64 by the reduction).
 static void launch_block_lowp(proxsdp_handle* H, const double* B, double* part) {
   dim3 grid(H->npad / 64, H->ch.nchunks);
+  if (H->prec == PROXSDP_BF16) {
+    const unsigned short* Wb = static_cast<const unsigned short*>(H->Wl);
+#define BB(KB) hipLaunchKernelGGL((k_block_partial_bf16<KB>), grid, dim3(256), 0, H->st, Wb, (int64_t)H->npad, B, H->k, part, H->ch.rows_per_chunk, H->npad)
+    switch (H->k / 16) {
+      case 1: BB(1); break;
+      case 2: BB(2); break;
+      case 3: BB(3); break;
+      default: BB(4); break;
+    }
+#undef BB
+    return;
+  }
   const float* Wf = static_cast<const float*>(H->Wl);
   switch (H->k / 16) {
     case 1: hipLaunchKernelGGL((k_block_partial_f32<1>), grid, dim3(256), 0, H->st, Wf, (int64_t)H->npad, B, H->k, part, H->ch.rows_per_chunk, H->npad); break;
@@ -740,7 +752,7 @@ static void launch_block_lowp(proxsdp_handle* H, const double* B, double* part) 
 // Z = W B applied exactly in FP64 from the factors of the current X, the
 // sparse part D and the rank-one terms (never reads the dense W), with the
 // per-slice Gram partials [B^T B, B^T Z, Z^T Z] for Rayleigh-Ritz.
-static void launch_implicit(proxsdp_handle* H, const double* B, double* Z) {
+static void launch_implicit(proxsdp_handle* H, const double* B, double* Z, bool grams = true) {
   hipStream_t st = H->st;
   const int pp = 1 - (H->iters & 1);       // factors of the current X
   const int r = H->iters > 0 ? H->r_old : 0;
@@ -754,9 +766,26 @@ static void launch_implicit(proxsdp_handle* H, const double* B, double* Z) {
   hipLaunchKernelGGL(k_implicit_rows, dim3(H->npad / 4), dim3(256), 0, st, H->dp, H->V[pp], r,
                      H->small, H->dval, B, k, Z);
   // Gram partials [B^T B, B^T Z, Z^T Z] per slice (a one-chunk reduction of Z)
-  launch_reduce(Z, 1, nullptr, B, nullptr, H->npad, k, H->gram_part, 0, 0.0, 1.0, true, st);
+  if (grams) launch_reduce(Z, 1, nullptr, B, nullptr, H->npad, k, H->gram_part, 0, 0.0, 1.0, true, st);
 }
 
+
+// Precision form: the low-precision W is written only when a dense filter
+// pass needs it (from the factors of the current X, the sparse part and the
+// rank-one terms, as the fused write at the end of an iteration would).
+static void ensure_w_fresh(proxsdp_handle* H) {
+  if (H->prec == PROXSDP_FP64 || H->w_fresh) return;
+  const int pp = 1 - (H->iters & 1);
+  const int r = H->iters > 0 ? H->r_old : 0;
+  prof_mark(H, H->ev_write, H->n_write, true);
+  launch_write(H, H->Wl, H->prec, H->npad, H->V[pp], r, lam_slot(pp), true, true, nullptr);
+  prof_mark(H, H->ev_write, H->n_write, false);
+  H->w_fresh = true;
+}
+
+// BF16 filter passes are used only while the eigen-accuracy target is looser
+// than the BF16 rounding level of W; exact passes (implicit operator) after.
+constexpr double BF16_ETA_FLOOR = 1e-2;
 
 // Reduces the residual partials of the last row-wise call and reads the
 // largest relative Ritz residual of the kept pairs (synchronises).
@@ -806,14 +835,22 @@ static void eig_iteration(proxsdp_handle* H, int par, int m) {
   for (int j = 0; j < m - 1; ++j) {
     int nxt = 0;
     while (nxt == cur || nxt == prev) ++nxt;
-    prof_mark(H, H->ev_pass, H->n_pass, true);
-    if (H->prec == PROXSDP_FP64)
-      launch_block(H->W, H->npad, H->n, H->npad, H->B[cur], H->k, H->part, H->ch, true, st);
-    else
-      launch_block_lowp(H, H->B[cur], H->part);
-    prof_mark(H, H->ev_pass, H->n_pass, false);
-    launch_reduce(H->part, H->ch.nchunks, H->B[nxt], H->B[cur], prev >= 0 ? H->B[prev] : nullptr,
-                  H->npad, H->k, H->gram_part, prev >= 0 ? 2 : 1, 0.0, 1.0, false, st, filt);
+    if (H->prec == PROXSDP_BF16 && H->eta < BF16_ETA_FLOOR) {
+      // exact filter pass: Z = W B from the factors, then the Chebyshev step
+      launch_implicit(H, H->B[cur], H->Z, false);
+      launch_reduce(H->Z, 1, H->B[nxt], H->B[cur], prev >= 0 ? H->B[prev] : nullptr, H->npad,
+                    H->k, H->gram_part, prev >= 0 ? 2 : 1, 0.0, 1.0, false, st, filt);
+    } else {
+      ensure_w_fresh(H);
+      prof_mark(H, H->ev_pass, H->n_pass, true);
+      if (H->prec == PROXSDP_FP64)
+        launch_block(H->W, H->npad, H->n, H->npad, H->B[cur], H->k, H->part, H->ch, true, st);
+      else
+        launch_block_lowp(H, H->B[cur], H->part);
+      prof_mark(H, H->ev_pass, H->n_pass, false);
+      launch_reduce(H->part, H->ch.nchunks, H->B[nxt], H->B[cur], prev >= 0 ? H->B[prev] : nullptr,
+                    H->npad, H->k, H->gram_part, prev >= 0 ? 2 : 1, 0.0, 1.0, false, st, filt);
+    }
     prev = cur;
     cur = nxt;
     H->passes += 1;
@@ -856,10 +893,16 @@ static void pattern_and_write(proxsdp_handle* H, int par, int ring_slot) {
   f.npat_blocks = H->npat_blocks;
   f.ring = H->ring;
   f.ring_slot = ring_slot;
-  prof_mark(H, H->ev_write, H->n_write, true);
-  launch_write(H, H->prec == PROXSDP_FP64 ? (void*)H->W : H->Wl, H->prec, H->npad, H->V[par], H->r,
-               lam_slot(par), true, true, &f);
-  prof_mark(H, H->ev_write, H->n_write, false);
+  if (H->prec == PROXSDP_FP64) {
+    prof_mark(H, H->ev_write, H->n_write, true);
+    launch_write(H, H->W, H->prec, H->npad, H->V[par], H->r, lam_slot(par), true, true, &f);
+    prof_mark(H, H->ev_write, H->n_write, false);
+  } else {
+    // precision form: finalise only; the low-precision W is written when a
+    // dense filter pass needs it
+    launch_write(H, H->Wl, H->prec, H->npad, H->V[par], H->r, lam_slot(par), true, true, &f, false);
+    H->w_fresh = false;
+  }
 }
 
 // One PDHG iteration (Algorithm 1 / Algorithm 2 inner loop).
