@@ -208,6 +208,9 @@ def main():
         "sweep_share_of_solve": round((pass_s + write_s) / max(sum(times), 1e-9), 3),
     })
     serving = serving_bench(args, dev) if args.serving else None
+    full_cmp = None
+    if args.workload != "snl" and n <= 4000 and not args.iters:
+        full_cmp = full_projection_cost(s, dev, sum(times) / len(times), last)
     prec = None
     if not args.no_precision_form and not args.iters and args.precision == "fp64":
         prec = {name: precision_form(prob, dev, opts, sum(times) / len(times), last, code)
@@ -241,6 +244,7 @@ def main():
         },
         "roofline": roofline,
         "precision_form": prec,
+        "full_eig_comparison": full_cmp,
         "serving": serving,
         "cpu_baseline": cpu,
     }
@@ -292,6 +296,33 @@ def serving_bench(args, dev):
     log(f"serving stream: p50 {out['p50_latency_s']}s p99 {out['p99_latency_s']}s, "
         f"{out['solves_per_s']} solves/s, {ok2}/{N} converged")
     return out
+
+
+def full_projection_cost(s, dev, t_lr, info):
+    """PD-SDP's exact projection on the GPU (rocSOLVER dsyevd + reconstruction
+    through proxsdp_project_psd with r = 0) timed on the solution's n x n
+    matrix, against the low-rank form's whole iteration."""
+    import torch
+    from paper_1810_05231_amd import project_psd
+    X, _ = s.solution(on_device=True)
+    project_psd(X, 0)          # warm-up (library handles, code objects)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        project_psd(X, 0)
+    torch.cuda.synchronize()
+    full_ms = (time.perf_counter() - t0) / reps * 1e3
+    lr_ms = t_lr / max(info["iters"], 1) * 1e3
+    log(f"exact projection (rocSOLVER) {full_ms:.2f} ms vs LR iteration {lr_ms:.3f} ms")
+    return {
+        "full_eig_projection_ms": round(full_ms, 3),
+        "lr_iteration_ms": round(lr_ms, 4),
+        "ratio": round(full_ms / lr_ms, 2),
+        "pd_sdp_projection_time_at_same_iters_s": round(full_ms * info["iters"] / 1e3, 2),
+        "note": "exact projection alone (no other work), per PDHG iteration, times the LR "
+                "iteration count; the LR figure is its whole iteration",
+    }
 
 
 def precision_form(prob, dev, opts, t64, info64, code):

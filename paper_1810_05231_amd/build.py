@@ -15,6 +15,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-Wno-unused-parameter",
     "-I", os.path.join(ROOT, "include"),
+    # the exact projection for n > 64 (PD-SDP comparison) uses rocSOLVER dsyevd
+    "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib",
 ]
 
 

@@ -16,6 +16,9 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "../../include/proxsdp.h"
 #include "common.hpp"
 #include "dense.hpp"
@@ -1448,6 +1451,140 @@ int proxsdp_get_solution(proxsdp_handle* H, double* X, double* y, int32_t on_dev
 // --------------------------------------------------------- projection only
 // Context of one stateless projection: the solver's buffers with an empty
 // constraint set.
+// ---------------------------------------- exact projection for n > KMAX
+// proj(S) of Section 2.3.2 through a full symmetric eigendecomposition
+// (rocSOLVER dsyevd, divide and conquer) and P = U+ U+^T with U+ the
+// eigenvectors of the positive eigenvalues scaled by sqrt(lambda) (rocBLAS
+// dgemm).  This is the PD-SDP projection the truncated one is compared with;
+// rocBLAS / rocSOLVER get their scratch from the caller's workspace.
+struct FullEig {
+  rocblas_handle h = nullptr;
+  int dev = -1;
+};
+static FullEig g_fulleig;
+
+static int fulleig_handle(rocblas_handle* out) {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (!g_fulleig.h || g_fulleig.dev != dev) {
+    if (g_fulleig.h) rocblas_destroy_handle(g_fulleig.h);
+    g_fulleig.h = nullptr;
+    if (rocblas_create_handle(&g_fulleig.h) != rocblas_status_success)
+      return fail(PROXSDP_ERR_HIP, "rocblas_create_handle failed");
+    g_fulleig.dev = dev;
+  }
+  *out = g_fulleig.h;
+  return PROXSDP_OK;
+}
+
+// Scratch of rocSOLVER dsyevd + rocBLAS dgemm for size n (bytes).
+static int fulleig_scratch(int n, size_t* bytes) {
+  rocblas_handle h;
+  int rc = fulleig_handle(&h);
+  if (rc) return rc;
+  if (rocblas_start_device_memory_size_query(h) != rocblas_status_success)
+    return fail(PROXSDP_ERR_HIP, "rocblas size query failed");
+  rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, nullptr, n, nullptr, nullptr,
+                   nullptr);
+  const double one = 1.0, zero = 0.0;
+  rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, n, n, n, &one, nullptr, n,
+                nullptr, n, &zero, nullptr, n);
+  size_t sz = 0;
+  if (rocblas_stop_device_memory_size_query(h, &sz) != rocblas_status_success)
+    return fail(PROXSDP_ERR_HIP, "rocblas size query failed");
+  *bytes = sz;
+  return PROXSDP_OK;
+}
+
+// Eigenvector rows scaled by sqrt(max(lambda, 0)): A holds the eigenvectors
+// as rows (dsyevd's column-major columns), D the eigenvalues.
+__global__ __launch_bounds__(256) void k_scale_evec_rows(const double* __restrict__ A,
+                                                         const double* __restrict__ D, int n,
+                                                         double* __restrict__ U) {
+  const int64_t cnt = (int64_t)n * n;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cnt;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(t / n);
+    const double lam = D[j];
+    U[t] = lam > 0.0 ? sqrt(lam) * A[t] : 0.0;
+  }
+}
+
+struct FullLayout {
+  double *A, *U, *D, *E;
+  int* info;
+  void* rb;
+  size_t rb_bytes;
+};
+
+static size_t full_layout(int n, size_t rb_bytes, void* ws, FullLayout* L) {
+  Carver c(ws);
+  L->A = c.take<double>((size_t)n * n);
+  L->U = c.take<double>((size_t)n * n);
+  L->D = c.take<double>(n);
+  L->E = c.take<double>(n);
+  L->info = c.take<int>(4);
+  L->rb = c.take<char>(std::max<size_t>(rb_bytes, 256));
+  L->rb_bytes = std::max<size_t>(rb_bytes, 256);
+  return c.off + 256;
+}
+
+static int project_full_large(const double* S, int n, int64_t lds, double tol_unused, double* P,
+                              int64_t ldp, double* evals, double* evecs, int32_t* rank_out,
+                              void* ws, size_t ws_bytes, hipStream_t st) {
+  (void)tol_unused;
+  size_t rb = 0;
+  int rc = fulleig_scratch(n, &rb);
+  if (rc) return rc;
+  FullLayout L{};
+  const size_t need = full_layout(n, rb, nullptr, &L);
+  if (ws_bytes < need) return fail(PROXSDP_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  full_layout(n, rb, ws, &L);
+  rocblas_handle h;
+  if ((rc = fulleig_handle(&h))) return rc;
+  if (rocblas_set_stream(h, st) != rocblas_status_success)
+    return fail(PROXSDP_ERR_HIP, "rocblas_set_stream failed");
+  if (rocblas_set_workspace(h, L.rb, L.rb_bytes) != rocblas_status_success)
+    return fail(PROXSDP_ERR_HIP, "rocblas_set_workspace failed");
+  HIP_OK(hipMemcpy2DAsync(L.A, (size_t)n * sizeof(double), S, (size_t)lds * sizeof(double),
+                          (size_t)n * sizeof(double), n, hipMemcpyDeviceToDevice, st));
+  if (rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, L.A, n, L.D, L.E, L.info) !=
+      rocblas_status_success)
+    return fail(PROXSDP_ERR_HIP, "rocsolver_dsyevd failed");
+  const int64_t cnt = (int64_t)n * n;
+  hipLaunchKernelGGL(k_scale_evec_rows, dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 4096)),
+                     dim3(256), 0, st, L.A, L.D, n, L.U);
+  if (P) {
+    // column-major view: U^T has the scaled eigenvectors as columns; P = U^T U
+    const double one = 1.0, zero = 0.0;
+    if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, n, n, n, &one, L.U, n,
+                      L.U, n, &zero, P, (rocblas_int)ldp) != rocblas_status_success)
+      return fail(PROXSDP_ERR_HIP, "rocblas_dgemm failed");
+  }
+  std::vector<double> D(n);
+  int info = 0;
+  HIP_OK(hipMemcpyAsync(D.data(), L.D, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(&info, L.info, sizeof(int), hipMemcpyDeviceToHost, st));
+  if (evecs) {
+    std::vector<double> A((size_t)n * n);
+    HIP_OK(hipMemcpyAsync(A.data(), L.A, A.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    for (int t = 0; t < n; ++t) {
+      const int j = n - 1 - t;   // descending
+      for (int i = 0; i < n; ++i) evecs[(size_t)i * n + t] = A[(size_t)j * n + i];
+    }
+  }
+  HIP_OK(hipStreamSynchronize(st));
+  if (info != 0) return fail(PROXSDP_ERR_HIP, "dsyevd did not converge (info " + std::to_string(info) + ")");
+  int pos = 0;
+  for (int t = 0; t < n; ++t) {
+    if (evals) evals[t] = D[n - 1 - t];
+    pos += D[n - 1 - t] > 0.0;
+  }
+  if (rank_out) *rank_out = pos;
+  return PROXSDP_OK;
+}
+
 static size_t project_layout(proxsdp_handle* H, int n, int r, void* ws, double** gpart) {
   H->n = n;
   H->npad = roundup(n, TILE);
@@ -1480,8 +1617,16 @@ int proxsdp_project_workspace_size(int32_t n, int32_t r, int32_t precision, size
   if (r < 0) return fail(PROXSDP_ERR_INVALID, "r must be >= 0");
   if (precision != PROXSDP_FP64) return fail(PROXSDP_ERR_UNSUPPORTED, "only PROXSDP_FP64 is built");
   const int re = (r == 0 || r >= n) ? n : r;
+  if (n > KMAX && re == n) {   // exact projection through rocSOLVER
+    size_t rb = 0;
+    const int rc = fulleig_scratch(n, &rb);
+    if (rc) return rc;
+    FullLayout L{};
+    *bytes = full_layout(n, rb, nullptr, &L);
+    return PROXSDP_OK;
+  }
   if (n > KMAX && re > 48)
-    return fail(PROXSDP_ERR_UNSUPPORTED, "for n > 64 the target rank must be <= 48");
+    return fail(PROXSDP_ERR_UNSUPPORTED, "for n > 64 the target rank must be <= 48 (or 0 / n for the exact projection)");
   proxsdp_handle H;
   double* g = nullptr;
   *bytes = project_layout(&H, n, re, nullptr, &g);
@@ -1504,6 +1649,9 @@ int proxsdp_project_psd(const void* S, int32_t n, int64_t lds, int32_t r, int32_
   if ((rc = set_lds_limits())) return rc;
   if (!(tol > 0)) tol = 1e-12;
   const int re = (r == 0 || r >= n) ? n : r;
+  if (n > KMAX && re == n)
+    return project_full_large(static_cast<const double*>(S), n, lds, tol, static_cast<double*>(P), ldp,
+                              evals, evecs, rank_out, ws, ws_bytes, static_cast<hipStream_t>(stream));
   proxsdp_handle H;
   H.st = static_cast<hipStream_t>(stream);
   double* gpart = nullptr;

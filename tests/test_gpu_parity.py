@@ -86,6 +86,26 @@ def test_project_partial_path(torch_cuda, n, r, rpos, seed):
     assert np.abs(S @ vec[:, :nchk] - vec[:, :nchk] * ev[:nchk]).max() <= 1e-9 * scale
 
 
+@pytest.mark.parametrize("n,rpos,seed", [(65, 5, 0), (300, 20, 1), (1000, 30, 2)])
+def test_project_exact_large(torch_cuda, n, rpos, seed):
+    """Exact projection (r = 0) beyond the single-workgroup size: rocSOLVER
+    eigendecomposition + reconstruction, against the oracle's proj."""
+    from paper_1810_05231_amd import project_psd
+    _say("project_exact_large", n, rpos, seed)
+    lam = I.lowrank_plus_negative_spectrum(n, rpos, seed)
+    S = I.random_symmetric(n, lam, seed)
+    St = torch_cuda.tensor(S, device="cuda")
+    P, ev, vec, rank = project_psd(St, 0, want_vectors=True)
+    want = O.proj_psd(S)
+    scale = np.abs(lam).max()
+    err = np.abs(P.cpu().numpy() - want).max()
+    _say("  max err", err)
+    assert err <= 1e-9 * scale
+    assert np.allclose(ev, np.sort(lam)[::-1], atol=1e-9 * scale)
+    assert rank == rpos
+    assert np.allclose(vec.T @ vec, np.eye(n), atol=1e-9)
+
+
 def test_project_ragged_leading_dimension(torch_cuda):
     from paper_1810_05231_amd import project_psd
     n = 131
