@@ -37,6 +37,11 @@ def log(*a):
 
 
 def main():
+    # the serving stream runs one HIP stream per in-flight solve; more hardware
+    # queues than HIP's default of 4 let more of them run concurrently (set
+    # before HIP initialises)
+    if "--serving" in sys.argv or "--serving-only" in sys.argv:
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
@@ -64,7 +69,7 @@ def main():
     ap.add_argument("--serving", type=int, default=0,
                     help="also run the serving stream with this many requests (0 = skip)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
-    ap.add_argument("--slots", type=int, default=8, help="serving: solves in flight")
+    ap.add_argument("--slots", type=int, default=16, help="serving: solves in flight")
     ap.add_argument("--budget-gib", type=float, default=32.0, help="serving: HBM budget")
     ap.add_argument("--no-precision-form", action="store_true",
                     help="skip the FP32 precision-form solve reported beside the FP64 result")
@@ -259,7 +264,7 @@ def serving_bench(args, dev):
     import instances as I
     from paper_1810_05231_amd.serving import Request, Server, percentile
     N = args.serving or 512
-    opts = dict(precision=1, tol=args.tol)
+    opts = dict(precision=1, tol=args.tol, graphs=1)
     srv = Server(device=dev, budget_bytes=int(args.budget_gib * (1 << 30)), max_slots=args.slots,
                  **opts)
     base = I.serving_stream(N, seed=args.seed, rate=None)

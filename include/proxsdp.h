@@ -123,6 +123,11 @@ typedef struct {
                            kept pairs is held below max(eig_tol * max|theta|,
                            eig_rel * alpha * eps_p), a fraction of the current
                            primal step (default 0.2)                              */
+  int32_t graphs;       /* 1: rounds of check_every iterations are captured once
+                           per configuration (rank, width, passes, ...) into HIP
+                           graphs and replayed (fewer launches; serving); needs
+                           a stream other than the null stream.  0 (default):
+                           every kernel is launched directly                    */
 } proxsdp_options;
 
 /* ------------------------------------------------------------- info */
@@ -174,16 +179,21 @@ int proxsdp_step(proxsdp_handle *h, int32_t n_iters, proxsdp_info *info);
  * numerical failure); fills *info (may be NULL).  Synchronises. */
 int proxsdp_solve(proxsdp_handle *h, proxsdp_info *info);
 
-/* Serving form: advances every handle in hs[0 .. count) that is still
- * running by n_iters PDHG iterations (fewer for a handle that stops).  The
- * iterations of all handles are enqueued between control checks, each on
- * its handle's own stream, so that solves of different sizes overlap on the
- * device; the control checks then synchronise each stream in turn.  Handles
- * created on the same stream are valid but run one after the other.
- * infos (host array of count entries, nullable) receives each handle's state.
- * Synchronises every stream before returning.  Errors: PROXSDP_ERR_INVALID
- * for a NULL handle array entry or n_iters < 0. */
-int proxsdp_step_many(proxsdp_handle **hs, int32_t count, int32_t n_iters, proxsdp_info *infos);
+/* Serving form: advances every running handle in hs[0 .. count) by up to
+ * n_iters PDHG iterations.  Handles progress independently: each one's next
+ * round (up to its next control check) is launched on its own stream as soon
+ * as its previous round has finished and been checked, so solves of different
+ * sizes overlap on the device and none waits for a slower one.  With flags &
+ * PROXSDP_STEP_UNTIL_ANY_STOPS the call returns once any handle stops
+ * (converged, limits), after the rounds in flight have finished; handles that
+ * did not finish their n_iters continue in the next call.  Handles on the same
+ * stream are valid but run one after the other.  infos (host array of count
+ * entries, nullable) receives each handle's state.  Synchronises every stream
+ * before returning.  Errors: PROXSDP_ERR_INVALID for a NULL entry or
+ * n_iters < 0. */
+#define PROXSDP_STEP_UNTIL_ANY_STOPS 1
+int proxsdp_step_many(proxsdp_handle **hs, int32_t count, int32_t n_iters, int32_t flags,
+                      proxsdp_info *infos);
 
 /* Current iterate: X (n x n, row-major, formed from the rank-r factors) and
  * the dual y (m + p values, unscaled, Section 1.3 sign).  Either pointer may

@@ -48,7 +48,7 @@ class Options(C.Structure):
         ("r_max", C.c_int32), ("full_eig", C.c_int32), ("precision", C.c_int32),
         ("max_iters", C.c_int32), ("time_limit_s", C.c_double), ("row_scaling", C.c_int32),
         ("block", C.c_int32), ("eig_tol", C.c_double), ("max_passes", C.c_int32),
-        ("seed", C.c_int32), ("eig_strict", C.c_int32), ("eig_rel", C.c_double),
+        ("seed", C.c_int32), ("eig_strict", C.c_int32), ("eig_rel", C.c_double), ("graphs", C.c_int32),
     ]
 
 
@@ -96,7 +96,7 @@ def _load():
         "proxsdp_profile_enable": (C.c_int, [H, C.c_int32]),
         "proxsdp_profile_read": (C.c_int, [H, _f64p, _i32p, _f64p, _i32p]),
         "proxsdp_profile_totals": (C.c_int, [H, _f64p, C.c_int32]),
-        "proxsdp_step_many": (C.c_int, [C.POINTER(H), C.c_int32, C.c_int32, C.c_void_p]),
+        "proxsdp_step_many": (C.c_int, [C.POINTER(H), C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
         "proxsdp_debug_scalars": (C.c_int, [H, _f64p, C.c_int32]),
         "proxsdp_rank_path": (C.c_int, [H, _i32p, _i32p, _i32p, C.c_int32, _i32p]),
         "proxsdp_last_error": (C.c_char_p, []),

@@ -65,6 +65,7 @@ enum Scalar {
   S_RRPATH,       // last Rayleigh-Ritz: Newton steps taken (>= 0) or -1 (Cholesky path)
   S_RRCHOL,       // number of Rayleigh-Ritz calls that took the Cholesky path
   S_RRCOUNT,      // number of Rayleigh-Ritz calls
+  S_ITER,         // iterations finalised (ring slot of the next record)
   S_COUNT
 };
 

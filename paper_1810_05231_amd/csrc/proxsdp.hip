@@ -12,7 +12,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -473,12 +475,26 @@ struct proxsdp_handle {
   double time_s = 0;
   proxsdp_info last{};
   size_t ws_need = 0;
+  // captured rounds of check_every iterations (opt.graphs)
+  struct GraphEntry {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    int end_bcur = 0, d_passes = 0;
+    bool end_wfresh = false;
+  };
+  std::map<std::tuple<int, int, int, int, int, int, int, int, int, int64_t>, GraphEntry> graphs;
   // optional kernel timing (benchmarks)
   bool prof = false;
   std::vector<hipEvent_t> ev_pass, ev_write;   // start/stop pairs
   std::vector<int> prof_k, prof_r;             // subspace width / rank of each timed launch
   int n_pass = 0, n_write = 0;
+  hipEvent_t round_ev = nullptr;   // end of the last round launched by step_many
   ~proxsdp_handle() {
+    if (round_ev) (void)hipEventDestroy(round_ev);
+    for (auto& kv : graphs) {
+      if (kv.second.ex) (void)hipGraphExecDestroy(kv.second.ex);
+      if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
+    }
     for (auto e : ev_pass) (void)hipEventDestroy(e);
     for (auto e : ev_write) (void)hipEventDestroy(e);
   }
@@ -802,6 +818,16 @@ static int x2_slot(int parity) { return SL::SC + S_X2 + parity; }
 
 // Eigensolver rounds on the current W with the current basis.  `final_round`
 // forms the factors V[par] and the partials; other rounds only update the basis.
+// Jacobi stopping level of the Rayleigh-Ritz step for the current accuracy
+// target, rounded down to a half decade (so that a captured round stays valid
+// while the target drifts within it).
+static double jacobi_tol(const proxsdp_handle* H) {
+  if (H->opt.eig_strict) return 1e-15;
+  double t = std::max(1e-15, std::min(1e-6, 0.01 * H->eta));
+  const double q = std::floor(std::log10(t) * 2.0) / 2.0;
+  return std::max(1e-15, std::pow(10.0, q));
+}
+
 static void eig_round(proxsdp_handle* H, int par, bool final_round) {
   hipStream_t st = H->st;
   const double* Bc = H->B[H->bcur];
@@ -816,8 +842,7 @@ static void eig_round(proxsdp_handle* H, int par, bool final_round) {
   } else {
     launch_implicit(H, Bc, H->Z);
   }
-  const double jac_tol = H->opt.eig_strict ? 1e-15 : std::max(1e-15, std::min(1e-6, 0.01 * H->eta));
-  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, jac_tol, st);
+  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, jacobi_tol(H), st);
   if (final_round)
     launch_rowwise(H, Bc, H->V[par], H->r, H->V[1 - par], H->r_old, Bn, st);
   else
@@ -870,8 +895,7 @@ static void eig_iteration(proxsdp_handle* H, int par, int m) {
     // precision form: the Rayleigh-Ritz pass applies W exactly (FP64 refinement)
     launch_implicit(H, H->B[cur], H->Z);
   }
-  const double jac_tol = std::max(1e-15, std::min(1e-6, 0.01 * H->eta));
-  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, jac_tol, st);
+  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, jacobi_tol(H), st);
   launch_rowwise(H, H->B[cur], H->V[par], H->r, H->V[1 - par], H->r_old, H->B[nb], st);
   H->bcur = nb;
   H->passes += 1;
@@ -941,9 +965,65 @@ static void iterate_once(proxsdp_handle* H) {
                      H->r, H->small, lam_slot(par), H->fac_part, H->full ? 1 : H->nsl, H->r_old,
                      H->y, H->y_old, H->MX, H->MX_old, H->row_part);
   // next W, residuals
-  pattern_and_write(H, par, H->iters % RING);
+  pattern_and_write(H, par, -1);   // ring slot from the device iteration counter
   H->r_old = H->r;
   H->iters += 1;
+}
+
+// Enqueues `count` iterations.  With opt.graphs, a round that starts at a
+// control check and spans check_every iterations is captured once per
+// configuration and replayed afterwards (same kernels, same arguments: every
+// quantity that varies between rounds of one configuration is read on the
+// device).
+static int run_round(proxsdp_handle* H, int count) {
+  // the legacy null stream cannot be captured: graphs need the handle on a
+  // stream of its own
+  const bool graphable = H->opt.graphs && H->st != nullptr && !H->opt.eig_strict && !H->prof &&
+                         !H->full && count == H->opt.check_every &&
+                         H->iters % H->opt.check_every == 0 && (H->opt.check_every % 2) == 0;
+  if (!graphable) {
+    for (int t = 0; t < count; ++t) iterate_once(H);
+    return PROXSDP_OK;
+  }
+  const bool lowp = H->prec == PROXSDP_BF16 && H->eta < BF16_ETA_FLOOR;
+  double jt = jacobi_tol(H);
+  int64_t jbits;
+  std::memcpy(&jbits, &jt, sizeof(jbits));
+  const auto key = std::make_tuple(H->bcur, H->r, H->r_old, H->k, H->m_rounds, H->prec,
+                                   (int)H->w_fresh, (int)lowp, count, jbits);
+  auto it = H->graphs.find(key);
+  if (it == H->graphs.end()) {
+    proxsdp_handle::GraphEntry e{};
+    const int bcur0 = H->bcur, passes0 = H->passes, iters0 = H->iters, rold0 = H->r_old;
+    const bool wf0 = H->w_fresh;
+    if (hipStreamBeginCapture(H->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();   // capture refused: clear the error, launch directly
+      H->opt.graphs = 0;
+      for (int t = 0; t < count; ++t) iterate_once(H);
+      return PROXSDP_OK;
+    }
+    for (int t = 0; t < count; ++t) iterate_once(H);
+    const hipError_t ce = hipStreamEndCapture(H->st, &e.g);
+    e.end_bcur = H->bcur;
+    e.d_passes = H->passes - passes0;
+    e.end_wfresh = H->w_fresh;
+    // nothing ran yet: restore the host state, then replay below
+    H->bcur = bcur0;
+    H->passes = passes0;
+    H->iters = iters0;
+    H->r_old = rold0;
+    H->w_fresh = wf0;
+    if (ce != hipSuccess) return fail(PROXSDP_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+    HIP_OK(hipGraphInstantiate(&e.ex, e.g, nullptr, nullptr, 0));
+    it = H->graphs.emplace(key, e).first;
+  }
+  HIP_OK(hipGraphLaunch(it->second.ex, H->st));
+  H->iters += count;
+  H->passes += it->second.d_passes;
+  H->bcur = it->second.end_bcur;
+  H->w_fresh = it->second.end_wfresh;
+  H->r_old = H->r;
+  return PROXSDP_OK;
 }
 
 static void set_rank(proxsdp_handle* H, int r_new, int why) {
@@ -1275,8 +1355,13 @@ int proxsdp_step(proxsdp_handle* H, int32_t n_iters, proxsdp_info* info) {
     H->time_s += std::chrono::duration<double>(now - t_last).count();
     t_last = now;
   };
-  for (int t = 0; t < n_iters && H->status == PROXSDP_STATUS_RUNNING; ++t) {
-    iterate_once(H);
+  int done = 0;
+  while (done < n_iters && H->status == PROXSDP_STATUS_RUNNING) {
+    const int ce = H->opt.check_every;
+    const int chunk = std::min(ce - H->iters % ce, n_iters - done);
+    const int rc0 = run_round(H, chunk);
+    if (rc0) return rc0;
+    done += chunk;
     if (H->iters % H->opt.check_every == 0) {
       const int rc = control(H);  // synchronises the stream
       if (rc) return rc;
@@ -1309,41 +1394,51 @@ int proxsdp_step(proxsdp_handle* H, int32_t n_iters, proxsdp_info* info) {
   return PROXSDP_OK;
 }
 
-int proxsdp_step_many(proxsdp_handle** hs, int32_t count, int32_t n_iters, proxsdp_info* infos) {
+int proxsdp_step_many(proxsdp_handle** hs, int32_t count, int32_t n_iters, int32_t flags,
+                      proxsdp_info* infos) {
   g_err.clear();
   if (count < 0 || (count > 0 && !hs)) return fail(PROXSDP_ERR_INVALID, "bad handle array");
   if (n_iters < 0) return fail(PROXSDP_ERR_INVALID, "n_iters < 0");
   for (int i = 0; i < count; ++i)
     if (!hs[i]) return fail(PROXSDP_ERR_INVALID, "handle " + std::to_string(i) + " is NULL");
-  auto t_last = std::chrono::steady_clock::now();
-  int remaining = n_iters;
-  while (remaining > 0) {
-    // enqueue up to the next control check of every running handle (each on
-    // its own stream, so that their kernels overlap on the device) ...
-    int chunk = remaining;
-    bool any = false;
-    for (int i = 0; i < count; ++i) {
-      proxsdp_handle* H = hs[i];
-      if (H->status != PROXSDP_STATUS_RUNNING) continue;
-      const int to_check = H->opt.check_every - H->iters % H->opt.check_every;
-      chunk = std::min(chunk, to_check);
-      any = true;
+  for (int i = 0; i < count; ++i)
+    if (!hs[i]->round_ev) HIP_OK(hipEventCreateWithFlags(&hs[i]->round_ev, hipEventDisableTiming));
+  std::vector<int> remaining(count, n_iters);
+  std::vector<char> in_flight(count, 0);
+  std::vector<std::chrono::steady_clock::time_point> t_start(count);
+  bool stop = false;
+  for (;;) {
+    // launch the next round of every idle running handle (each on its own stream)
+    if (!stop) {
+      for (int i = 0; i < count; ++i) {
+        proxsdp_handle* H = hs[i];
+        if (in_flight[i] || H->status != PROXSDP_STATUS_RUNNING || remaining[i] <= 0) continue;
+        const int ce = H->opt.check_every;
+        const int chunk = std::min(ce - H->iters % ce, remaining[i]);
+        t_start[i] = std::chrono::steady_clock::now();
+        const int rc = run_round(H, chunk);
+        if (rc) return rc;
+        HIP_OK(hipEventRecord(H->round_ev, H->st));
+        remaining[i] -= chunk;
+        in_flight[i] = 1;
+      }
     }
-    if (!any) break;
+    bool any_in_flight = false;
+    // completed rounds: control check at once, independently of the others
     for (int i = 0; i < count; ++i) {
+      if (!in_flight[i]) continue;
       proxsdp_handle* H = hs[i];
-      if (H->status != PROXSDP_STATUS_RUNNING) continue;
-      for (int t = 0; t < chunk; ++t) iterate_once(H);
-    }
-    // ... then the checks, in handle order (each synchronises its own stream)
-    for (int i = 0; i < count; ++i) {
-      proxsdp_handle* H = hs[i];
-      if (H->status != PROXSDP_STATUS_RUNNING) continue;
+      const hipError_t q = hipEventQuery(H->round_ev);
+      if (q == hipErrorNotReady) {
+        any_in_flight = true;
+        continue;
+      }
+      if (q != hipSuccess) return fail(PROXSDP_ERR_HIP, std::string("round event: ") + hipGetErrorString(q));
+      in_flight[i] = 0;
+      H->time_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start[i]).count();
       if (H->iters % H->opt.check_every == 0) {
         const int rc = control(H);
         if (rc) return rc;
-        const auto t = std::chrono::steady_clock::now();
-        H->time_s += std::chrono::duration<double>(t - t_last).count();
         if (H->status == PROXSDP_STATUS_RUNNING && H->iters >= H->opt.max_iters)
           H->status = PROXSDP_STATUS_MAX_ITERS;
         if (H->status == PROXSDP_STATUS_RUNNING && H->opt.time_limit_s > 0 &&
@@ -1351,10 +1446,14 @@ int proxsdp_step_many(proxsdp_handle** hs, int32_t count, int32_t n_iters, proxs
           H->status = PROXSDP_STATUS_TIME_LIMIT;
         H->last.status = H->status;
         H->last.time_s = H->time_s;
+        if (H->status != PROXSDP_STATUS_RUNNING && (flags & PROXSDP_STEP_UNTIL_ANY_STOPS)) stop = true;
       }
     }
-    t_last = std::chrono::steady_clock::now();
-    remaining -= chunk;
+    bool more = false;
+    if (!stop)
+      for (int i = 0; i < count; ++i)
+        more |= hs[i]->status == PROXSDP_STATUS_RUNNING && remaining[i] > 0 && !in_flight[i];
+    if (!any_in_flight && !more) break;
   }
   for (int i = 0; i < count; ++i) {
     proxsdp_handle* H = hs[i];

@@ -285,7 +285,14 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     rec.lambda_r1 = sc[S_LAMR1];
     rec.maxres = sc[S_MAXRES];
     rec.normw = sc[S_NORMW];
-    f.ring[f.ring_slot] = rec;
+    // ring slot: given (set-up record) or the device iteration counter, so
+    // that a captured round of iterations can be replayed
+    int slot = f.ring_slot;
+    if (slot < 0) {
+      slot = (int)sc[S_ITER] % RING;
+      sc[S_ITER] += 1.0;
+    }
+    f.ring[slot] = rec;
   }
 }
 

@@ -4,10 +4,12 @@ Requests (an SDP instance and an arrival time) are admitted in arrival order
 while the summed device footprint of the admitted solves (their workspace,
 `proxsdp_workspace_size`) stays within a budget and a slot (stream) is free.
 Every admitted solve keeps its whole state (W, factors and Ritz basis, y, the
-problem data) resident in its own workspace and runs on its own HIP stream;
-`proxsdp_step_many` advances all of them between control checks so that their
-kernels overlap on the device.  A finished solve releases its slot and its
-memory at once, and waiting requests are admitted in the same round.
+problem data) resident in its own workspace and runs on its own HIP stream,
+with its check rounds replayed from captured HIP graphs; `proxsdp_step_many`
+lets every solve progress independently (a round is relaunched as soon as the
+previous one has been checked), so their kernels overlap on the device and no
+request waits for a slower one.  The call returns as soon as a solve stops; its
+slot and memory go to waiting requests at once.
 
 Only orchestration lives here (arrival clock, admission, bookkeeping); every
 iteration runs in libproxsdp.
@@ -66,11 +68,13 @@ class Server:
     solver_options: proxsdp_options fields for every solve (e.g. precision=1).
     """
 
-    def __init__(self, device="cuda", budget_bytes=32 << 30, max_slots=16, **solver_options):
+    def __init__(self, device="cuda", budget_bytes=32 << 30, max_slots=16, round_iters=100,
+                 **solver_options):
         import torch
         self.device = torch.device(device)
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
+        self.round_iters = int(round_iters)   # iterations per step_many call (upper bound)
         self.opts = dict(solver_options)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.max_slots)]
         self.peak_bytes = 0
@@ -114,7 +118,9 @@ class Server:
                     if wait > 0:
                         time.sleep(min(wait, 0.05))
                 continue
-            infos = step_many([a[1] for a in active], self.opts.get("check_every", 10))
+            # every solve progresses on its own; return as soon as one stops so
+            # that its slot and memory go to a waiting request at once
+            infos = step_many([a[1] for a in active], self.round_iters, until_any_stops=True)
             still = []
             for a, info in zip(active, infos):
                 req, s, si, t_adm, fp = a

@@ -181,16 +181,22 @@ class Solver:
         self._buf = None
 
 
-def step_many(solvers, n_iters: int):
-    """Advances several solvers (each on its own stream) by n_iters iterations
-    with their kernels interleaved on the device; returns their info dicts."""
+STEP_UNTIL_ANY_STOPS = 1
+
+
+def step_many(solvers, n_iters: int, until_any_stops: bool = False):
+    """Advances several solvers (each on its own stream) by up to n_iters
+    iterations, each progressing independently on the device; with
+    until_any_stops the call returns once one of them stops.  Returns their
+    info dicts."""
     cnt = len(solvers)
     if cnt == 0:
         return []
     hs = (C.c_void_p * cnt)(*[s._h.value for s in solvers])
     infos = (Info * cnt)()
-    check(lib.proxsdp_step_many(hs, cnt, int(n_iters), C.cast(infos, C.c_void_p)),
-          "proxsdp_step_many")
+    check(lib.proxsdp_step_many(hs, cnt, int(n_iters),
+                                STEP_UNTIL_ANY_STOPS if until_any_stops else 0,
+                                C.cast(infos, C.c_void_p)), "proxsdp_step_many")
     return [infos[i].to_dict() for i in range(cnt)]
 
     def __del__(self):

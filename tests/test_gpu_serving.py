@@ -36,6 +36,28 @@ def _requests():
     return reqs
 
 
+@pytest.mark.parametrize("kind,n,prec", [("maxcut", 300, 0), ("equip", 200, 1), ("maxcut", 400, 2)])
+def test_graph_rounds_match_eager(torch_cuda, kind, n, prec):
+    """Rounds replayed from captured HIP graphs (many replays, with the control
+    checks' synchronisations and host reads between them) give bitwise the
+    eager launches' results."""
+    from paper_1810_05231_amd.solver import Solver
+    prob = I.maxcut(n, 0.05, 11) if kind == "maxcut" else I.equipartition(n, 0.05, 11)
+    a = Solver(prob, precision=prec)
+    ia = a.solve()
+    b = Solver(prob, precision=prec, graphs=1, stream=torch_cuda.cuda.Stream())
+    ib = b.solve()
+    _say("  eager", ia["iters"], repr(ia["obj"]), " graphs", ib["iters"], repr(ib["obj"]))
+    assert ia["status_name"] == ib["status_name"] == "converged"
+    assert ia["iters"] == ib["iters"] and ia["passes"] == ib["passes"]
+    assert ib["obj"] == ia["obj"]
+    Xa, ya = a.solution(on_device=False)
+    Xb, yb = b.solution(on_device=False)
+    assert np.array_equal(Xa, Xb) and np.array_equal(ya, yb)
+    a.close()
+    b.close()
+
+
 def test_step_many_matches_step(torch_cuda):
     """proxsdp_step_many over several handles == proxsdp_step on each."""
     from paper_1810_05231_amd.solver import Solver, step_many
@@ -47,7 +69,7 @@ def test_step_many_matches_step(torch_cuda):
         info = s.step(200)
         alone.append(info)
         s.close()
-    mix = [Solver(prob, stream=st, precision=1) for (_, _, prob), st in zip(reqs, streams)]
+    mix = [Solver(prob, stream=st, precision=1, graphs=1) for (_, _, prob), st in zip(reqs, streams)]
     infos = step_many(mix, 200)
     for a, b in zip(alone, infos):
         _say("  alone", a["iters"], repr(a["obj"]), " mix", b["iters"], repr(b["obj"]))
@@ -68,7 +90,7 @@ def test_serving_alone_vs_mix(torch_cuda):
         alone[rid] = info
         s.close()
     # budget for about three of the six at a time: later requests queue for memory
-    srv = Server(max_slots=4, precision=1)
+    srv = Server(max_slots=4, precision=1, graphs=1)
     fps = sorted(srv.footprint(p) for _, _, p in reqs)
     srv.budget = fps[-1] + fps[-2] + fps[-3]
     certs = {}
