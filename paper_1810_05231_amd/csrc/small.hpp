@@ -420,11 +420,10 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
     }
     __syncthreads();
     double offR = 1.0, offS = 1.0, smax = 1.0;
-    int st = 0;
-    for (;; ++st) {
-      for (int t = tid; t < k; t += nt) mu[t] = Sc[t * ld + t] / Gc[t * ld + t];
-      __syncthreads();
-      // important pairs: those touching a positive value among the r largest
+    // important pairs: those touching a positive value among the r largest.
+    // Ranked once here from the starting values and once more for the
+    // acceptance test (the steps keep the set).
+    auto rank_important = [&]() {
       for (int t = tid; t < k; t += nt) {
         const double v = mu[t];
         int rank = 0;
@@ -433,14 +432,26 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
         if (rank == (r < k ? r : k) - 1) red[15] = v;   // r-th largest
       }
       __syncthreads();
+    };
+    for (int t = tid; t < k; t += nt) mu[t] = Sc[t * ld + t] / Gc[t * ld + t];
+    __syncthreads();
+    rank_important();
+    int st = 0;
+    for (;; ++st) {
+      // statistics of the current step; the diagonal's owners refresh mu
       double aR = 0.0, aS = 0.0, mx = 0.0;
       RR_FOR_KK(t, i, j) {
         const double rij = ((i == j) ? 1.0 : 0.0) - Gc[i * ld + j];
         aR += rij * rij;
-        if (i == j) mx = fmax(mx, fabs(mu[i]));
-        else if (imp[i] || imp[j]) aS += Sc[i * ld + j] * Sc[i * ld + j];
+        if (i == j) {
+          const double m_i = Sc[i * ld + i] / Gc[i * ld + i];
+          mu[i] = m_i;
+          mx = fmax(mx, fabs(m_i));
+        } else if (imp[i] || imp[j]) {
+          aS += Sc[i * ld + j] * Sc[i * ld + j];
+        }
       }
-      block_sum2_max1(aR, aS, mx, red);
+      block_sum2_max1(aR, aS, mx, red);   // its barriers also publish mu
       offR = sqrt(aR);
       offS = sqrt(aS);
       smax = fmax(mx, 1e-300);
@@ -469,10 +480,15 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
     }
     newton_ok = offR <= 1e-12 && offS <= 1e-4 * smax;
     if (newton_ok) {
-      // The unwanted tail is not diagonalised, so its block may hide an
-      // eigenvalue above the kept ones.  Gershgorin bound of that block:
-      // accept only if no tail eigenvalue can exceed max(mu_(r), 0).
-      double z0 = 0.0, z1 = 0.0, gb = 0.0;
+      // re-rank on the final values; the kept couplings are re-measured on
+      // that set, and the unwanted tail, not diagonalised, may hide an
+      // eigenvalue above the kept ones: Gershgorin bound of the tail block,
+      // accepted only if no tail eigenvalue can exceed max(mu_(r), 0).
+      rank_important();
+      double aS = 0.0, z1 = 0.0, gb = 0.0;
+      RR_FOR_KK(t, i, j) {
+        if (i != j && (imp[i] || imp[j])) aS += Sc[i * ld + j] * Sc[i * ld + j];
+      }
       for (int i = tid; i < k; i += nt) {
         if (imp[i]) continue;
         double rad = 0.0;
@@ -481,8 +497,8 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
         gb = fmax(gb, mu[i] + rad);
       }
       const double thr = fmax(red[15], 0.0);
-      block_sum2_max1(z0, z1, gb, red);   // max(gb, 0) over the tail rows
-      newton_ok = gb <= thr;
+      block_sum2_max1(aS, z1, gb, red);   // sum over the kept pairs, max(gb, 0) over the tail
+      newton_ok = gb <= thr && sqrt(aS) <= 1e-4 * smax;
     }
     if (newton_ok) path = st;
   }
