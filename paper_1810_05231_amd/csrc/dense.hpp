@@ -601,17 +601,46 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
   const int a0 = I * TILE, b0 = J * TILE;
   const int nq = rank1 ? dp.n_r1 : 0;
   const int rr = r + nq;
-  double* sT = sm;                        // 64 x 65 output tile
+  // LDS: first the scaled factor rows of the column block (64 x rr, row
+  // stride LDVB, rr <= KMAX + MAX_R1), staged once for the four waves with
+  // coalesced loads; then, in the same memory, the 64 x 64 output tile.
+  constexpr int LDVB = KMAX + MAX_R1 + 1;
+  double* sVb = sm;
+  double* sT = sm;
   const double* lam = small + lam_off;
   const double alpha = small[SL::SC + S_ALPHA];
-  // low-rank part on MFMA f64 16x16x4: wave w owns rows [16w, 16w + 16) of the
-  // tile; operands straight from the factors (L2 resident), 16 contraction
-  // indices per batch with all loads issued before the MFMAs:
-  //   A[m][q] = Vrow(a0 + 16w + m)[q],  B[q][c] = s_q Vrow(b0 + 16nb + c)[q]
-  // with s_q = lambda_q for factor columns and alpha sigma_u y_u for the
-  // rank-one terms u = q - r.
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
+  // lane q of a wave holds column q (and q + 64) of a row: factor columns
+  // scaled by lambda_q, then the rank-one terms scaled by
+  // gamma_u = alpha sigma_u y_u
+  for (int half = 0; half < 2; ++half) {
+    const int q = lane + 64 * half;
+    if (half == 1 && rr <= 64) break;
+    double sc = 0.0;
+    const double* uu = nullptr;
+    if (q < r) {
+      sc = lam[q];
+    } else if (q < rr) {
+      const int u = q - r;
+      sc = alpha * dp.r1_sigma[u] * y[dp.r1_row[u]];
+      uu = dp.r1_u + (int64_t)u * dp.npad;
+    }
+    if (q < LDVB) {
+      for (int row = w; row < TILE; row += 4) {
+        const int gb = b0 + row;
+        double v = 0.0;
+        if (q < r) v = V[(int64_t)gb * ldv + q] * sc;
+        else if (q < rr) v = uu[gb] * sc;
+        sVb[row * LDVB + q] = v;
+      }
+    }
+  }
+  __syncthreads();
+  // low-rank part on MFMA f64 16x16x4: wave w owns rows [16w, 16w + 16) of the
+  // tile; A from the factor rows of the row block (16 contraction indices per
+  // batch, loads issued before the MFMAs), B from the staged block:
+  //   A[m][q] = Vrow(a0 + 16w + m)[q],  B[q][c] = s_q Vrow(b0 + 16nb + c)[q]
   {
     d4 acc[4];
 #pragma unroll
@@ -619,34 +648,25 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
     const int m = lane & 15, kq = lane >> 4;
     const int arow = a0 + 16 * w + m;
     for (int t0 = 0; t0 < rr; t0 += 16) {
-      double av[4], bv[4][4];
+      double av[4];
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
         const int q = t0 + 4 * s4 + kq;
-        if (q < r) {
-          const double sc = lam[q];
-          av[s4] = V[(int64_t)arow * ldv + q];
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb) bv[s4][nb] = V[(int64_t)(b0 + 16 * nb + m) * ldv + q] * sc;
-        } else if (q < rr) {
-          const int u = q - r;
-          const double sc = alpha * dp.r1_sigma[u] * y[dp.r1_row[u]];
-          const double* uu = dp.r1_u + (int64_t)u * dp.npad;
-          av[s4] = uu[arow];
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb) bv[s4][nb] = uu[b0 + 16 * nb + m] * sc;
-        } else {
-          av[s4] = 0.0;
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb) bv[s4][nb] = 0.0;
-        }
+        if (q < r) av[s4] = V[(int64_t)arow * ldv + q];
+        else if (q < rr) av[s4] = dp.r1_u[(int64_t)(q - r) * dp.npad + arow];
+        else av[s4] = 0.0;
       }
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4)
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int q = t0 + 4 * s4 + kq;
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb)
-          acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bv[s4][nb], acc[nb], 0, 0, 0);
+        for (int nb = 0; nb < 4; ++nb) {
+          const double bv = (q < rr) ? sVb[(16 * nb + m) * LDVB + q] : 0.0;
+          acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bv, acc[nb], 0, 0, 0);
+        }
+      }
     }
+    __syncthreads();   // every wave is done with the staged rows
     // result lane l, register v: row l/16 + 4 v, column l % 16
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {

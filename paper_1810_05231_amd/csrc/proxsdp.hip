@@ -424,9 +424,12 @@ struct Chunking {
   int rows_per_chunk, nchunks;
 };
 
+// Row chunks of the dense pass: about 512 workgroups in total (measured at
+// n = 5000, k = 64: the Gram reduction of the chunk partials falls from 67 to
+// 47 us against ~1024 workgroups, with the pass itself unchanged).
 Chunking chunking(int npad) {
   const int cols = npad / 64;
-  const int target = std::max(1, (1024 + cols - 1) / cols);
+  const int target = std::max(1, (512 + cols - 1) / cols);
   int R = roundup((npad + target - 1) / target, 64);
   R = std::max(R, 64);
   return {R, (npad + R - 1) / R};
@@ -726,7 +729,8 @@ static void launch_write(proxsdp_handle* H, void* Wout, int out_prec, int64_t ld
                          int r, int lam_off, bool sparse, bool rank1, const FinArgs* fin,
                          bool tiles = true) {
   const int ts = H->npad / TILE;
-  const size_t lds = (size_t)TILE * (TILE + 1) * sizeof(double);
+  // staged factor block (TILE x (KMAX + MAX_R1 + 1)), reused for the output tile
+  const size_t lds = (size_t)TILE * (KMAX + MAX_R1 + 1) * sizeof(double);
   FinArgs f{};
   if (fin) f = *fin;
   const dim3 grid((tiles ? ts * (ts + 1) / 2 : 0) + (fin ? 1 : 0));
