@@ -110,6 +110,8 @@ constexpr int FAC_RES = 2 * KMAX * KMAX + MAX_R1 * KMAX;   // Ritz residual norm
 constexpr int FAC_STRIDE = FAC_RES + KMAX;
 constexpr int VB_STRIDE = KMAX * KMAX + MAX_R1 * KMAX;  // per-slice partials of V^T B, u^T B
 constexpr int ROW_PART = 4;                 // eps_d^2, <dMX, dy>, dual obj, nonfinite
+constexpr int ROW_LANES = 8;                // threads per constraint row in the dual step
+constexpr int ROWS_PER_BLOCK = 256 / ROW_LANES;
 constexpr int PAT_PART = 4 + MAX_R1;        // min gersh, ||M*dy||^2 (sparse), obj, unused, cross_q
 
 // Number of SLICE-row workgroups covering npad rows.

@@ -595,7 +595,7 @@ static void setup_dims(proxsdp_handle* H) {
   H->k = H->full ? 16 : (H->opt.block ? H->opt.block : k_for_r(H->r));
   H->ch = chunking(h.npad);
   H->nsl = n_slices(h.npad);
-  H->nrow_blocks = (h.rows + 255) / 256;
+  H->nrow_blocks = (h.rows + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
   H->npat_blocks = std::min(1024, (h.n + 3) / 4);
 }
 
@@ -965,7 +965,7 @@ static void iterate_once(proxsdp_handle* H) {
     }
   }
   // dual step
-  hipLaunchKernelGGL(k_gather_dual, dim3(H->nrow_blocks), dim3(256), 0, st, H->dp, H->V[par],
+  hipLaunchKernelGGL(k_gather_dual, dim3(H->nrow_blocks), dim3(ROW_LANES * ROWS_PER_BLOCK), 0, st, H->dp, H->V[par],
                      H->r, H->small, lam_slot(par), H->fac_part, H->full ? 1 : H->nsl, H->r_old,
                      H->y, H->y_old, H->MX, H->MX_old, H->row_part);
   // next W, residuals

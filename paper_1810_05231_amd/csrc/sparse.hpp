@@ -76,24 +76,35 @@ __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double
   }
   const double* lam = small + lam_off;
   const double alpha = small[SL::SC + S_ALPHA];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // ROW_LANES threads per row: each sums the factor columns t = sub (mod
+  // ROW_LANES) of every entry of the row, then a shuffle reduction
+  const int sub = threadIdx.x % ROW_LANES;
+  const int i = blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / ROW_LANES;
   double ed2 = 0.0, cross = 0.0, dobj = 0.0, bad = 0.0;
+  double mx = 0.0;
   if (i < dp.rows) {
-    double mx = 0.0;
-    for (int e = dp.row_ptr[i]; e < dp.row_ptr[i + 1]; ++e)
-      mx += dp.row_w[e] * factor_entry(V, lam, r, dp.row_a[e], dp.row_b[e]);
+    for (int e = dp.row_ptr[i]; e < dp.row_ptr[i + 1]; ++e) {
+      const double* va = V + (int64_t)dp.row_a[e] * KMAX;
+      const double* vb = V + (int64_t)dp.row_b[e] * KMAX;
+      double acc = 0.0;
+      for (int t = sub; t < r; t += ROW_LANES) acc += lam[t] * va[t] * vb[t];
+      mx += dp.row_w[e] * acc;
+    }
     const int q = dp.row_r1[i];
     if (q >= 0) {
       // sigma_q u_q^T X+ u_q = sigma_q sum_t lam_t (u_q^T v_t)^2
       const int off = r * r + r * r_old + q * r;
       double acc = 0.0;
-      for (int t = 0; t < r; ++t) {
+      for (int t = sub; t < r; t += ROW_LANES) {
         double uv = 0.0;
         for (int s = 0; s < nslices; ++s) uv += fac_part[(int64_t)s * FAC_STRIDE + off + t];
         acc += lam[t] * uv * uv;
       }
       mx += dp.r1_sigma[q] * acc;
     }
+  }
+  for (int o = ROW_LANES / 2; o > 0; o >>= 1) mx += __shfl_xor(mx, o);
+  if (i < dp.rows && sub == 0) {
     const double mx0 = MX[i];
     const double y0 = y[i];
     double u = y0 + alpha * (dp.rhs[i] - (2.0 * mx - mx0));
