@@ -689,7 +689,7 @@ static void launch_reduce(const double* part, int nchunks, double* Z, const doub
 }
 
 #ifndef PROXSDP_RR_THREADS
-#define PROXSDP_RR_THREADS 256
+#define PROXSDP_RR_THREADS 512
 #endif
 
 // jac_tol: relative off-diagonal level at which the Jacobi sweeps stop.

@@ -363,16 +363,20 @@ __device__ __forceinline__ double lds_dot(const double* a, int sa, const double*
   return (s0 + s1) + (s2 + s3);
 }
 
+// Scratch doubles of k_small_rr's reductions: 3 per wave (up to 16 waves) and
+// one slot (the last) for the r-th largest value.
+constexpr int RR_RED = 3 * 16 + 1;
+
 // LDS doubles of k_small_rr for subspace width k.
 __host__ __device__ inline size_t small_rr_lds_doubles(int k) {
-  return 4 * (size_t)k * (k + 1) + 4 * KMAX + 3 * (KMAX / 2 + 1) + 16;
+  return 4 * (size_t)k * (k + 1) + 4 * KMAX + 3 * (KMAX / 2 + 1) + RR_RED;
 }
 
 #define RR_FOR_KK(t, i, j)                              \
   for (int t = tid; t < (k << 6); t += nt)              \
     if (const int j = t & 63, i = t >> 6; j < k)
 
-__global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, int k, int r,
+__global__ __launch_bounds__(512) void k_small_rr(double* __restrict__ small, int k, int r,
                                                   int lam_off, int filter, double jac_tol,
                                                   int oa_steps) {
   extern __shared__ double sm[];
@@ -387,8 +391,9 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
   double* inv = vals + KMAX;      // KMAX
   double* mu = inv + KMAX;        // KMAX
   double* cs = mu + KMAX;         // 3 * (KMAX/2 + 1)
-  double* red = cs + 3 * (KMAX / 2 + 1);   // 16
-  int* perm = reinterpret_cast<int*>(red + 16);
+  double* red = cs + 3 * (KMAX / 2 + 1);   // RR_RED
+  double* mu_r = red + RR_RED - 1;          // r-th largest mu (Newton path)
+  int* perm = reinterpret_cast<int*>(red + RR_RED);
   int* flag = perm + KMAX;  // [0] dropped count, [1] jacobi
   int* imp = flag + 4;      // KMAX: pair importance on the Newton path
   const double* G = small + SL::GG;
@@ -429,7 +434,7 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
         int rank = 0;
         for (int j = 0; j < k; ++j) rank += (mu[j] > v) || (mu[j] == v && j < t);
         imp[t] = (rank < r && v > 0.0) ? 1 : 0;
-        if (rank == (r < k ? r : k) - 1) red[15] = v;   // r-th largest
+        if (rank == (r < k ? r : k) - 1) *mu_r = v;   // r-th largest
       }
       __syncthreads();
     };
@@ -496,7 +501,7 @@ __global__ __launch_bounds__(256) void k_small_rr(double* __restrict__ small, in
           if (j != i && !imp[j]) rad += fabs(Sc[i * ld + j]);
         gb = fmax(gb, mu[i] + rad);
       }
-      const double thr = fmax(red[15], 0.0);
+      const double thr = fmax(*mu_r, 0.0);
       block_sum2_max1(aS, z1, gb, red);   // sum over the kept pairs, max(gb, 0) over the tail
       newton_ok = gb <= thr && sqrt(aS) <= 1e-4 * smax;
     }
