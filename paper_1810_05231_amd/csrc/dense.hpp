@@ -248,7 +248,7 @@ __device__ inline void gram_blocks_mfma(const double* X, const double* Y, int k,
 // Sums partials into Z, optional Chebyshev step, Gram partials per slice.
 //   cheb 0: Z = W B;   1: Z = (W B - c B) / e;   2: Z = 2 (W B - c B) / e - Bprev
 // Z == nullptr: Z is not stored (Gram partials of a product that already exists).
-__global__ __launch_bounds__(256) void k_reduce_gram(const double* __restrict__ part, int nchunks,
+__global__ __launch_bounds__(512) void k_reduce_gram(const double* __restrict__ part, int nchunks,
                                                      double* __restrict__ Z,
                                                      const double* __restrict__ B,
                                                      const double* __restrict__ Bprev, int npad,
@@ -266,18 +266,38 @@ __global__ __launch_bounds__(256) void k_reduce_gram(const double* __restrict__ 
   const int64_t base = (int64_t)s * SLICE * k;
   const int cnt = SLICE * k;
   const int64_t cstride = (int64_t)npad * k;
-  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+  // pairs of elements (16-byte loads); the chunk partials of each element are
+  // summed in chunk order with eight loads in flight at a time
+  for (int t = 2 * threadIdx.x; t < cnt; t += 2 * blockDim.x) {
     const int64_t off = base + t;
-    double z = 0.0;
-    for (int c = 0; c < nchunks; ++c) z += part[c * cstride + off];
-    const double b = B[off];
-    if (cheb == 1)
-      z = (z - cc * b) / ce;
-    else if (cheb == 2)
-      z = 2.0 * (z - cc * b) / ce - Bprev[off];
-    if (Z) Z[off] = z;
-    sZ[t] = z;
-    sB[t] = b;
+    double2 z = make_double2(0.0, 0.0);
+    for (int c = 0; c < nchunks; c += 8) {
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = (c + u < nchunks) ? *reinterpret_cast<const double2*>(part + (c + u) * cstride + off)
+                                 : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c + u < nchunks) {
+          z.x += v[u].x;
+          z.y += v[u].y;
+        }
+    }
+    const double2 b = *reinterpret_cast<const double2*>(B + off);
+    if (cheb == 1) {
+      z.x = (z.x - cc * b.x) / ce;
+      z.y = (z.y - cc * b.y) / ce;
+    } else if (cheb == 2) {
+      const double2 bp = *reinterpret_cast<const double2*>(Bprev + off);
+      z.x = 2.0 * (z.x - cc * b.x) / ce - bp.x;
+      z.y = 2.0 * (z.y - cc * b.y) / ce - bp.y;
+    }
+    if (Z) *reinterpret_cast<double2*>(Z + off) = z;
+    sZ[t] = z.x;
+    sZ[t + 1] = z.y;
+    sB[t] = b.x;
+    sB[t + 1] = b.y;
   }
   if (!grams) return;
   __syncthreads();
@@ -294,18 +314,24 @@ __global__ __launch_bounds__(256) void k_reduce_gram(const double* __restrict__ 
 // strides keep the 16 lanes of an MFMA operand column on distinct banks).
 __device__ inline d4 mfma_rows_times_small(const double* Xl, int ldx, int row0,
                                            const double* Sg, int ldS, int col0, int k, d4 acc) {
-  // acc[m][n] += sum_q Xl[row0 + m][q] * Sg[q][col0 + n]
+  // acc[m][n] += sum_q Xl[row0 + m][q] * Sg[q][col0 + n]; the global operand
+  // column is loaded whole before the products (one memory latency per job)
   const int lane = threadIdx.x & 63;
   const int m = lane & 15, kq = lane >> 4;
-  for (int q0 = 0; q0 < k; q0 += 4) {
-    const double a = Xl[(row0 + m) * ldx + q0 + kq];
-    const double b = Sg[(q0 + kq) * ldS + col0 + m];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  double bq[KMAX / 4];
+#pragma unroll
+  for (int q = 0; q < KMAX / 4; ++q) bq[q] = (4 * q < k) ? Sg[(4 * q + kq) * ldS + col0 + m] : 0.0;
+#pragma unroll
+  for (int q = 0; q < KMAX / 4; ++q) {
+    if (4 * q < k) {
+      const double a = Xl[(row0 + m) * ldx + 4 * q + kq];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq[q], acc, 0, 0, 0);
+    }
   }
   return acc;
 }
 
-__global__ __launch_bounds__(256) void k_rowwise(const double* __restrict__ B,
+__global__ __launch_bounds__(512) void k_rowwise(const double* __restrict__ B,
                                                  const double* __restrict__ Z,
                                                  const double* __restrict__ small, int k,
                                                  double* __restrict__ V, int r,
@@ -320,6 +346,7 @@ __global__ __launch_bounds__(256) void k_rowwise(const double* __restrict__ B,
   double* sZ = sB + SLICE * ldk;     // SLICE x ldk
   double* sV = sZ + SLICE * ldk;     // SLICE x ldr
   double* sZS = sV + SLICE * ldr;    // SLICE x ldr
+  double* sU = sZS + SLICE * ldr;    // n_r1 x SLICE: rank-one vectors on the slice
   const int s = blockIdx.x;
   const int i0 = s * SLICE;
   const int64_t base = (int64_t)i0 * k;
@@ -328,6 +355,9 @@ __global__ __launch_bounds__(256) void k_rowwise(const double* __restrict__ B,
     sB[i * ldk + c] = B[base + t];
     sZ[i * ldk + c] = Z[base + t];
   }
+  if (V)
+    for (int t = threadIdx.x; t < n_r1 * SLICE; t += blockDim.x)
+      sU[t] = r1_u[(int64_t)(t / SLICE) * npad + i0 + (t % SLICE)];
   __syncthreads();
   const double* S = small + SL::S;
   const double* MZ = small + SL::MZ;
@@ -366,14 +396,23 @@ __global__ __launch_bounds__(256) void k_rowwise(const double* __restrict__ B,
   __syncthreads();
   double* out = fac_part + (int64_t)s * FAC_STRIDE;
   const double* theta = small + SL::THETA;
-  for (int c = threadIdx.x; c < r; c += blockDim.x) {
-    const double th = theta[c];
+  // residual norms: eight lanes per column, SLICE / 8 rows each, combined by
+  // a fixed butterfly
+  for (int c0 = 0; c0 < r; c0 += (int)blockDim.x / 8) {
+    const int c = c0 + (int)(threadIdx.x >> 3), part = threadIdx.x & 7;
+    const int cc = c < r ? c : 0;
+    const double th = theta[cc];
     double acc = 0.0;
-    for (int i = 0; i < SLICE; ++i) {
-      const double d = sZS[i * ldr + c] - th * sV[i * ldr + c];
+#pragma unroll
+    for (int j = 0; j < SLICE / 8; ++j) {
+      const int i = part * (SLICE / 8) + j;
+      const double d = sZS[i * ldr + cc] - th * sV[i * ldr + cc];
       acc += d * d;
     }
-    out[FAC_RES + c] = acc;
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 4);
+    if (c < r && part == 0) out[FAC_RES + c] = acc;
   }
   if (!V) return;
   // factor Grams on MFMA: V^T V (rb x rb blocks) and V^T Vold (rb x rob blocks)
@@ -386,11 +425,20 @@ __global__ __launch_bounds__(256) void k_rowwise(const double* __restrict__ B,
     const int jb = old ? job - rb * rb : job;
     const int nbk = old ? rob : rb;
     const int a0 = (jb / nbk) * 16, b0 = (jb - (jb / nbk) * nbk) * 16;
-    for (int q0 = 0; q0 < SLICE; q0 += 4) {
-      const double a = sV[(q0 + kq) * ldr + a0 + m];
-      const double b = old ? ((b0 + m < r_old) ? Vold[(int64_t)(i0 + q0 + kq) * KMAX + b0 + m] : 0.0)
-                           : sV[(q0 + kq) * ldr + b0 + m];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    double bq[SLICE / 4];
+    if (old) {
+      const bool in = b0 + m < r_old;
+#pragma unroll
+      for (int q = 0; q < SLICE / 4; ++q)
+        bq[q] = in ? Vold[(int64_t)(i0 + 4 * q + kq) * KMAX + b0 + m] : 0.0;
+    } else {
+#pragma unroll
+      for (int q = 0; q < SLICE / 4; ++q) bq[q] = sV[(4 * q + kq) * ldr + b0 + m];
+    }
+#pragma unroll
+    for (int q = 0; q < SLICE / 4; ++q) {
+      const double a = sV[(4 * q + kq) * ldr + a0 + m];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq[q], acc, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -406,7 +454,7 @@ __global__ __launch_bounds__(256) void k_rowwise(const double* __restrict__ B,
   for (int t = threadIdx.x; t < n_r1 * r; t += blockDim.x) {
     const int q = t / r, a = t - (t / r) * r;
     double acc = 0.0;
-    for (int i = 0; i < SLICE; ++i) acc += r1_u[(int64_t)q * npad + i0 + i] * sV[i * ldr + a];
+    for (int i = 0; i < SLICE; ++i) acc += sU[q * SLICE + i] * sV[i * ldr + a];
     out[n1 + n2 + t] = acc;
   }
 }

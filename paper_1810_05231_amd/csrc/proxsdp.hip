@@ -684,7 +684,7 @@ static void launch_reduce(const double* part, int nchunks, double* Z, const doub
                           double cc, double ce, bool grams, hipStream_t st,
                           const double* filt = nullptr) {
   const size_t lds = 2 * (size_t)SLICE * k * sizeof(double);
-  hipLaunchKernelGGL(k_reduce_gram, dim3(n_slices(npad)), dim3(256), lds, st, part, nchunks, Z, B,
+  hipLaunchKernelGGL(k_reduce_gram, dim3(n_slices(npad)), dim3(512), lds, st, part, nchunks, Z, B,
                      Bprev, npad, k, gram_part, cheb, cc, ce, grams ? 1 : 0, filt);
 }
 
@@ -707,8 +707,9 @@ static void launch_rr(const double* gram_part, int nsl, double* small, int k, in
 static void launch_rowwise(proxsdp_handle* H, const double* B, double* V, int r, const double* Vold,
                            int r_old, double* Bn, hipStream_t st) {
   const int rp = (r + 15) & ~15;
-  const size_t lds = (2 * (size_t)SLICE * (H->k + 1) + 2 * (size_t)SLICE * (rp + 1)) * sizeof(double);
-  hipLaunchKernelGGL(k_rowwise, dim3(H->nsl), dim3(256), lds, st, B, H->Z, H->small, H->k, V, r,
+  const size_t lds = (2 * (size_t)SLICE * (H->k + 1) + 2 * (size_t)SLICE * (rp + 1) +
+                      (size_t)MAX_R1 * SLICE) * sizeof(double);
+  hipLaunchKernelGGL(k_rowwise, dim3(H->nsl), dim3(512), lds, st, B, H->Z, H->small, H->k, V, r,
                      Vold, r_old, Bn, H->dp.n_r1, H->dp.r1_u, H->npad, H->fac_part);
 }
 
