@@ -596,7 +596,7 @@ static void setup_dims(proxsdp_handle* H) {
   H->ch = chunking(h.npad);
   H->nsl = n_slices(h.npad);
   H->nrow_blocks = (h.rows + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
-  H->npat_blocks = std::min(1024, (h.n + 3) / 4);
+  H->npat_blocks = std::min(4096, (h.n + 3) / 4);
 }
 
 static void fill_dev_problem(proxsdp_handle* H) {

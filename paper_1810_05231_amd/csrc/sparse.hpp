@@ -42,15 +42,6 @@ __device__ inline double block_min(double v, double* red) {
   return s;
 }
 
-// X+_{ab} from the factors (V row stride KMAX).
-__device__ inline double factor_entry(const double* V, const double* lam, int r, int a, int b) {
-  const double* va = V + (int64_t)a * KMAX;
-  const double* vb = V + (int64_t)b * KMAX;
-  double acc = 0.0;
-  for (int t = 0; t < r; ++t) acc += lam[t] * va[t] * vb[t];
-  return acc;
-}
-
 __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double* __restrict__ V,
                                                      int r, double* __restrict__ small,
                                                      int lam_off, const double* __restrict__ fac_part,
@@ -136,7 +127,11 @@ __device__ inline double wave_sum(double v) {
 }
 
 // One wave per row a of the symmetric pattern (rows strided over the grid);
-// lanes split the row's entries.
+// lanes split the row's entries.  The objective term of the row,
+//   sum over owned entries e = (a, b) of w_e C_e X+_ab
+//     = sum_t lambda_t V_at g_t,   g_t = sum_e w_e C_e V_bt,
+// is formed with lanes over t: each entry's b and w_e C_e are broadcast from
+// the lane that holds it and the wave reads factor row b coalesced.
 __global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __restrict__ V, int r,
                                                  const double* __restrict__ small, int lam_off,
                                                  const double* __restrict__ y,
@@ -153,31 +148,50 @@ __global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __
   for (int q = 0; q < MAX_R1; ++q) crossq[q] = 0.0;
   for (int a = blockIdx.x * 4 + wave; a < dp.n; a += gridDim.x * 4) {
     double center = 0.0, radius = 0.0;
-    for (int s = dp.sym_ptr[a] + lane; s < dp.sym_ptr[a + 1]; s += 64) {
-      const int e = dp.sym_e[s];
-      const int ea = dp.pat_a[e], eb = dp.pat_b[e];
-      double dv = -alpha * dp.pat_c[e];
-      double md = 0.0;
-      for (int t = dp.pat_rptr[e]; t < dp.pat_rptr[e + 1]; ++t) {
-        const int i = dp.pat_row[t];
-        const double v = dp.pat_val[t];
-        const double yi = y[i];
-        dv += alpha * yi * v;
-        md += (yi - y_old[i]) * v;
+    double g = 0.0;   // lane t: sum over the owned entries of w_e C_e V_bt
+    const int s0 = dp.sym_ptr[a], s1 = dp.sym_ptr[a + 1];
+    for (int base = s0; base < s1; base += 64) {
+      const int s = base + lane;
+      double wc = 0.0;
+      int bb = 0;
+      if (s < s1) {
+        const int e = dp.sym_e[s];
+        const int ea = dp.pat_a[e], eb = dp.pat_b[e];
+        const double ce = dp.pat_c[e];
+        double dv = -alpha * ce;
+        double md = 0.0;
+        for (int t = dp.pat_rptr[e]; t < dp.pat_rptr[e + 1]; ++t) {
+          const int i = dp.pat_row[t];
+          const double v = dp.pat_val[t];
+          const double yi = y[i];
+          dv += alpha * yi * v;
+          md += (yi - y_old[i]) * v;
+        }
+        if (ea == eb)
+          center += dv;
+        else
+          radius += fabs(dv);
+        if (ea == a) {  // owner of the entry
+          dval[e] = dv;
+          const double w = (ea == eb) ? 1.0 : 2.0;
+          mdy2 += w * md * md;
+          for (int q = 0; q < dp.n_r1; ++q)
+            crossq[q] += w * md * dp.r1_u[(int64_t)q * dp.npad + ea] * dp.r1_u[(int64_t)q * dp.npad + eb];
+          wc = w * ce;
+          bb = eb;
+        }
       }
-      if (ea == eb)
-        center += dv;
-      else
-        radius += fabs(dv);
-      if (ea == a) {  // owner of the entry
-        dval[e] = dv;
-        const double w = (ea == eb) ? 1.0 : 2.0;
-        mdy2 += w * md * md;
-        for (int q = 0; q < dp.n_r1; ++q)
-          crossq[q] += w * md * dp.r1_u[(int64_t)q * dp.npad + ea] * dp.r1_u[(int64_t)q * dp.npad + eb];
-        if (with_obj && dp.pat_c[e] != 0.0) obj += w * dp.pat_c[e] * factor_entry(V, lam, r, ea, eb);
+      if (with_obj) {
+        const int cnt = min(64, s1 - base);
+#pragma unroll 8
+        for (int j = 0; j < cnt; ++j) {
+          const double wcj = __shfl(wc, j);
+          const int bj = __shfl(bb, j);
+          if (wcj != 0.0 && lane < r) g += wcj * V[(int64_t)bj * KMAX + lane];
+        }
       }
     }
+    if (with_obj && lane < r) obj += lam[lane] * V[(int64_t)a * KMAX + lane] * g;
     center = wave_sum(center);
     radius = wave_sum(radius);
     lo = fmin(lo, center - radius);
