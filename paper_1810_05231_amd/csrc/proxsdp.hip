@@ -424,14 +424,14 @@ struct Chunking {
   int rows_per_chunk, nchunks;
 };
 
-// Row chunks of the dense pass: about 512 workgroups in total (measured at
-// n = 5000, k = 64: the Gram reduction of the chunk partials falls from 67 to
-// 47 us against ~1024 workgroups, with the pass itself unchanged).
+// Row chunks of the dense pass: about 704 workgroups in total, ~2.75 per CU
+// of the 256 (measured at n = 5000, k = 64 with 7 / 9 / 12 chunks: 93 / 86 /
+// 90 us; the Gram reduction of the partials grows by ~1 us per chunk).
 Chunking chunking(int npad) {
   const int cols = npad / 64;
-  const int target = std::max(1, (512 + cols - 1) / cols);
-  int R = roundup((npad + target - 1) / target, 64);
-  R = std::max(R, 64);
+  const int steps = npad / 64;
+  const int c = std::min(std::max(1, (704 + cols / 2) / cols), steps);
+  const int R = ((steps + c - 1) / c) * 64;
   return {R, (npad + R - 1) / R};
 }
 
@@ -648,7 +648,10 @@ static int set_lds_limits() {
   if (done) return PROXSDP_OK;
   int rc;
   if ((rc = set_lds_one((const void*)k_reduce_gram))) return rc;
-  if ((rc = set_lds_one((const void*)k_small_rr))) return rc;
+  if ((rc = set_lds_one((const void*)k_small_rr<4>))) return rc;
+  if ((rc = set_lds_one((const void*)k_small_rr<8>))) return rc;
+  if ((rc = set_lds_one((const void*)k_small_rr<12>))) return rc;
+  if ((rc = set_lds_one((const void*)k_small_rr<16>))) return rc;
   if ((rc = set_lds_one((const void*)k_rowwise))) return rc;
   if ((rc = set_lds_one((const void*)k_full_eig))) return rc;
   if ((rc = set_lds_one((const void*)k_write_w<double>))) return rc;
@@ -688,9 +691,6 @@ static void launch_reduce(const double* part, int nchunks, double* Z, const doub
                      Bprev, npad, k, gram_part, cheb, cc, ce, grams ? 1 : 0, filt);
 }
 
-#ifndef PROXSDP_RR_THREADS
-#define PROXSDP_RR_THREADS 512
-#endif
 
 // jac_tol: relative off-diagonal level at which the Jacobi sweeps stop.
 // oa_steps: largest number of Newton refinement steps before the Cholesky path.
@@ -700,8 +700,16 @@ static void launch_rr(const double* gram_part, int nsl, double* small, int k, in
   hipLaunchKernelGGL(k_sum_grams, dim3((3 * kk + 255) / 256), dim3(256), 0, st, gram_part, nsl, k,
                      small);
   const size_t lds = small_rr_lds_doubles(k) * sizeof(double) + (2 * KMAX + 4) * sizeof(int);
-  hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(PROXSDP_RR_THREADS), lds, st, small, k, r, lam_off,
-                     filter, jac_tol, oa_steps);
+#define RR_LAUNCH(KQ)                                                                    \
+  hipLaunchKernelGGL(k_small_rr<KQ>, dim3(1), dim3(RR_THREADS), lds, st, small, k, r, lam_off, \
+                     filter, jac_tol, oa_steps)
+  switch (k) {
+    case 16: RR_LAUNCH(4); break;
+    case 32: RR_LAUNCH(8); break;
+    case 48: RR_LAUNCH(12); break;
+    default: RR_LAUNCH(16); break;
+  }
+#undef RR_LAUNCH
 }
 
 static void launch_rowwise(proxsdp_handle* H, const double* B, double* V, int r, const double* Vold,

@@ -289,6 +289,115 @@ __device__ __forceinline__ void strip_mm(double* Out, int ldo, const double* X, 
   }
 }
 
+// Threads of k_small_rr (eight waves; the Newton step below assumes it).
+constexpr int RR_THREADS = 512;
+
+// One Newton step's products, in place:  G <- F^T G F,  S <- F^T S F,  X <- X F
+// (k x k in LDS, row stride ld, k = 4 KQ), eight waves.  Wave w < 2 kb owns
+// column block b of G (w even) or S (w odd), b = kb - 1 - w / 2: it forms the
+// column block (M F)[:, b] in registers, whose MFMA output layout is already
+// the B-operand layout of the second product, and then the blocks a <= b of
+// F^T (M F) (the rest by symmetry).  The kb^2 tiles of X F go to the waves
+// from the last one down.  Everything is read before the first barrier and
+// written after it; the second barrier publishes the per-wave partial sums of
+// ||I - G||_F^2 and of the important off-diagonal S entries, returned in
+// aR and aS (fixed summation order).
+template <int KQ>
+__device__ __forceinline__ void newton_products(double* G, double* S, const double* F, double* X,
+                                                int ld, const int* imp, double* red, double& aR,
+                                                double& aS) {
+  constexpr int kb = KQ / 4;
+  constexpr int NW = RR_THREADS / 64;
+  constexpr int XT = (kb * kb + NW - 1) / NW;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
+  const bool mjob = wave < 2 * kb;
+  const bool isS = wave & 1;
+  const int b = kb - 1 - (wave >> 1);
+  double* M = isS ? S : G;
+  d4 res[kb];
+  d4 xres[XT];
+  if (mjob) {
+    // (M F)[:, b]: the F operand column block is shared by the kb tiles
+    double bv[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) bv[q] = F[(4 * q + kq) * ld + b * 16 + m];
+    d4 tcol[kb];
+#pragma unroll
+    for (int a = 0; a < kb; ++a) {
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < KQ; ++q)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[(a * 16 + m) * ld + 4 * q + kq], bv[q], acc, 0, 0, 0);
+      tcol[a] = acc;
+    }
+    // F^T (M F)[:, b]: lane value v of tile a is row 16 a + kq + 4 v of the
+    // column block, i.e. the B operand of k-step q = 4 a + v
+#pragma unroll
+    for (int a = 0; a < kb; ++a) {
+      if (a > b) continue;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < KQ; ++q)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(F[(4 * q + kq) * ld + a * 16 + m], tcol[q >> 2][q & 3],
+                                                   acc, 0, 0, 0);
+      res[a] = acc;
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < XT; ++x) {
+    const int t = NW - 1 - wave + x * NW;
+    if (t < kb * kb) xres[x] = tile_mm<KQ>(X, ld, false, F, ld, (t / kb) * 16, (t % kb) * 16, m, kq);
+  }
+  __syncthreads();
+  double pr = 0.0, ps = 0.0;
+  if (mjob) {
+#pragma unroll
+    for (int a = 0; a < kb; ++a) {
+      if (a > b) continue;
+      const double wgt = (a != b) ? 2.0 : 1.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = a * 16 + kq + 4 * v, col = b * 16 + m;
+        const double val = res[a][v];
+        M[row * ld + col] = val;
+        if (a != b) M[col * ld + row] = val;
+        if (!isS) {
+          const double rij = ((row == col) ? 1.0 : 0.0) - val;
+          pr += wgt * rij * rij;
+        } else if (row != col && (imp[row] || imp[col])) {
+          ps += wgt * val * val;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < XT; ++x) {
+    const int t = NW - 1 - wave + x * NW;
+    if (t < kb * kb) {
+      const int a0 = (t / kb) * 16, b0 = (t % kb) * 16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[(a0 + kq + 4 * v) * ld + b0 + m] = xres[x][v];
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    pr += __shfl_xor(pr, o);
+    ps += __shfl_xor(ps, o);
+  }
+  if (lane == 0) {
+    red[2 * wave] = pr;
+    red[2 * wave + 1] = ps;
+  }
+  __syncthreads();
+  aR = 0.0;
+  aS = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    aR += red[2 * w];
+    aS += red[2 * w + 1];
+  }
+}
+
 // Deterministic workgroup reduction of (sum a, sum b, max(c, 0)); every thread
 // gets the result.  `red` is LDS scratch of 3 * (blockDim / 64) doubles.
 __device__ __forceinline__ void block_sum2_max1(double& a, double& b, double& c, double* red) {
@@ -376,7 +485,9 @@ __host__ __device__ inline size_t small_rr_lds_doubles(int k) {
   for (int t = tid; t < (k << 6); t += nt)              \
     if (const int j = t & 63, i = t >> 6; j < k)
 
-__global__ __launch_bounds__(512) void k_small_rr(double* __restrict__ small, int k, int r,
+// KQN = k / 4 (the kernel is instantiated per subspace width).
+template <int KQN>
+__global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ small, int k, int r,
                                                   int lam_off, int filter, double jac_tol,
                                                   int oa_steps) {
   extern __shared__ double sm[];
@@ -417,11 +528,11 @@ __global__ __launch_bounds__(512) void k_small_rr(double* __restrict__ small, in
     double* Gc = B0;
     double* Sc = B1;
     double* F = B2;
-    double* Tm = B3;
+    double* Xc = B3;   // accumulated coefficients X (G-orthonormalising, diagonalising)
     RR_FOR_KK(t, i, j) {
       Gc[i * ld + j] = 0.5 * (G[i * k + j] + G[j * k + i]) * d[i] * d[j];
       Sc[i * ld + j] = 0.5 * (T[i * k + j] + T[j * k + i]) * d[i] * d[j];
-      Sg[i * KMAX + j] = (i == j) ? 1.0 : 0.0;
+      Xc[i * ld + j] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
     double offR = 1.0, offS = 1.0, smax = 1.0;
@@ -441,27 +552,32 @@ __global__ __launch_bounds__(512) void k_small_rr(double* __restrict__ small, in
     for (int t = tid; t < k; t += nt) mu[t] = Sc[t * ld + t] / Gc[t * ld + t];
     __syncthreads();
     rank_important();
+    // statistics of the starting matrices; later steps form them in the
+    // epilogue of their products
+    double aR = 0.0, aS = 0.0, mx = 0.0;
+    RR_FOR_KK(t, i, j) {
+      const double rij = ((i == j) ? 1.0 : 0.0) - Gc[i * ld + j];
+      aR += rij * rij;
+      if (i == j)
+        mx = fmax(mx, fabs(mu[i]));
+      else if (imp[i] || imp[j])
+        aS += Sc[i * ld + j] * Sc[i * ld + j];
+    }
+    block_sum2_max1(aR, aS, mx, red);
+    // G-orthonormality is needed to a level tied to the eigen-accuracy
+    // target (it bounds the error of the factors), not to the last ulp; a
+    // stagnating defect below 1e-12 is taken as converged as well.
+    const double rtol = fmax(1e-13, 1e-3 * jac_tol);
+    double offR_prev = 1.0;
     int st = 0;
     for (;; ++st) {
-      // statistics of the current step; the diagonal's owners refresh mu
-      double aR = 0.0, aS = 0.0, mx = 0.0;
-      RR_FOR_KK(t, i, j) {
-        const double rij = ((i == j) ? 1.0 : 0.0) - Gc[i * ld + j];
-        aR += rij * rij;
-        if (i == j) {
-          const double m_i = Sc[i * ld + i] / Gc[i * ld + i];
-          mu[i] = m_i;
-          mx = fmax(mx, fabs(m_i));
-        } else if (imp[i] || imp[j]) {
-          aS += Sc[i * ld + j] * Sc[i * ld + j];
-        }
-      }
-      block_sum2_max1(aR, aS, mx, red);   // its barriers also publish mu
       offR = sqrt(aR);
       offS = sqrt(aS);
       smax = fmax(mx, 1e-300);
-      const bool conv = offR <= 1e-13 && offS <= fmax(jac_tol, 1e-15) * smax;
+      const bool rdone = offR <= rtol || (offR <= 1e-12 && offR > 0.25 * offR_prev);
+      const bool conv = rdone && offS <= fmax(jac_tol, 1e-15) * smax;
       if (conv || st == oa_steps || !(offR < 0.5) || !isfinite(offS) || !isfinite(smax)) break;
+      offR_prev = offR;
       const double delta = 2.0 * (offS + smax * offR);
       RR_FOR_KK(t, i, j) {
         const double rij = ((i == j) ? 1.0 : 0.0) - Gc[i * ld + j];
@@ -473,17 +589,22 @@ __global__ __launch_bounds__(512) void k_small_rr(double* __restrict__ small, in
         F[i * ld + j] = ((i == j) ? 1.0 : 0.0) + e;
       }
       __syncthreads();
-      lds_mm(Tm, ld, Gc, ld, false, F, ld, k);
-      __syncthreads();
-      lds_mm(Gc, ld, F, ld, true, Tm, ld, k, true);
-      __syncthreads();
-      lds_mm(Tm, ld, Sc, ld, false, F, ld, k);
-      __syncthreads();
-      lds_mm(Sc, ld, F, ld, true, Tm, ld, k, true);
-      strip_mm(Sg, KMAX, Sg, KMAX, F, ld, nullptr, nullptr, k);
+      newton_products<KQN>(Gc, Sc, F, Xc, ld, imp, red, aR, aS);
+      // Rayleigh quotients of the new pairs; every wave forms max |mu| itself
+      {
+        const int lane = tid & 63;
+        double v = 0.0;
+        if (lane < k) {
+          v = Sc[lane * ld + lane] / Gc[lane * ld + lane];
+          if (tid < k) mu[lane] = v;
+        }
+        double a = fabs(v);
+        for (int o = 32; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o));
+        mx = a;
+      }
       __syncthreads();
     }
-    newton_ok = offR <= 1e-12 && offS <= 1e-4 * smax;
+    newton_ok = offR <= fmax(1e-12, rtol) && offS <= 1e-4 * smax;
     if (newton_ok) {
       // re-rank on the final values; the kept couplings are re-measured on
       // that set, and the unwanted tail, not diagonalised, may hide an
@@ -589,7 +710,7 @@ __global__ __launch_bounds__(512) void k_small_rr(double* __restrict__ small, in
   sort_desc(B1, ld, k, vals, perm);
   if (newton_ok) {
     // coefficients D X U[:, perm] into B0 (X^T G X is no longer needed)
-    strip_mm(B0, ld, Sg, KMAX, B2, ld, perm, d, k);
+    strip_mm(B0, ld, B3, ld, B2, ld, perm, d, k);
     __syncthreads();
     Sbuf = B0;
     Pbuf = B1;
