@@ -182,14 +182,20 @@ __device__ __forceinline__ void sort_desc(const double* A, int lda, int k, doubl
     perm[i] = i;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    const double v = A[i * lda + i];
+  // eight lanes per entry, each counting over every eighth competitor
+  for (int i0 = 0; i0 < k; i0 += (int)blockDim.x / 8) {
+    const int i = i0 + (int)(threadIdx.x >> 3), part = threadIdx.x & 7;
+    const int ii = i < k ? i : k - 1;
+    const double v = A[ii * lda + ii];
     int rank = 0;
-    for (int j = 0; j < k; ++j) {
+    for (int j = part; j < k; j += 8) {
       const double u = A[j * lda + j];
-      rank += (u > v) || (u == v && j < i);
+      rank += (u > v) || (u == v && j < ii);
     }
-    if (rank < k) {
+    rank += __shfl_xor(rank, 1);
+    rank += __shfl_xor(rank, 2);
+    rank += __shfl_xor(rank, 4);
+    if (i < k && part == 0 && rank < k) {
       vals[rank] = v;
       perm[rank] = i;
     }
@@ -540,12 +546,20 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
     // Ranked once here from the starting values and once more for the
     // acceptance test (the steps keep the set).
     auto rank_important = [&]() {
-      for (int t = tid; t < k; t += nt) {
-        const double v = mu[t];
+      // eight lanes per value, each counting over every eighth competitor
+      for (int t0 = 0; t0 < k; t0 += nt / 8) {
+        const int t = t0 + (tid >> 3), part = tid & 7;
+        const int tt = t < k ? t : k - 1;
+        const double v = mu[tt];
         int rank = 0;
-        for (int j = 0; j < k; ++j) rank += (mu[j] > v) || (mu[j] == v && j < t);
-        imp[t] = (rank < r && v > 0.0) ? 1 : 0;
-        if (rank == (r < k ? r : k) - 1) *mu_r = v;   // r-th largest
+        for (int j = part; j < k; j += 8) rank += (mu[j] > v) || (mu[j] == v && j < tt);
+        rank += __shfl_xor(rank, 1);
+        rank += __shfl_xor(rank, 2);
+        rank += __shfl_xor(rank, 4);
+        if (t < k && part == 0) {
+          imp[t] = (rank < r && v > 0.0) ? 1 : 0;
+          if (rank == (r < k ? r : k) - 1) *mu_r = v;   // r-th largest
+        }
       }
       __syncthreads();
     };
@@ -615,12 +629,16 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
       RR_FOR_KK(t, i, j) {
         if (i != j && (imp[i] || imp[j])) aS += Sc[i * ld + j] * Sc[i * ld + j];
       }
-      for (int i = tid; i < k; i += nt) {
-        if (imp[i]) continue;
+      for (int i0 = 0; i0 < k; i0 += nt / 8) {
+        const int i = i0 + (tid >> 3), part = tid & 7;
+        const int ii = i < k ? i : k - 1;
         double rad = 0.0;
-        for (int j = 0; j < k; ++j)
-          if (j != i && !imp[j]) rad += fabs(Sc[i * ld + j]);
-        gb = fmax(gb, mu[i] + rad);
+        for (int j = part; j < k; j += 8)
+          if (j != ii && !imp[j]) rad += fabs(Sc[ii * ld + j]);
+        rad += __shfl_xor(rad, 1);
+        rad += __shfl_xor(rad, 2);
+        rad += __shfl_xor(rad, 4);
+        if (i < k && part == 0 && !imp[i]) gb = fmax(gb, mu[i] + rad);
       }
       const double thr = fmax(*mu_r, 0.0);
       block_sum2_max1(aS, z1, gb, red);   // sum over the kept pairs, max(gb, 0) over the tail
@@ -772,11 +790,13 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
     }
   }
   const double gam = filter ? fmax(fabs(vals[0] - fc), fe) : scale;
+  double resc = 0.0;   // column tid's residual (k <= 64: wave 0 holds them all)
   for (int c = tid; c < k; c += nt) {
     const double sps = lds_dot(Sbuf + c, ld, Ybuf + c, ld, k);
     const double th = vals[c];
     theta[c] = th;
-    res[c] = sqrt(fmax(sps - th * th, 0.0)) / scale;
+    resc = sqrt(fmax(sps - th * th, 0.0)) / scale;
+    res[c] = resc;
     // column scale of the next basis: the predicted norm ||(W - cI) v|| (with
     // v^T W v = theta), floored at 1e-7 of the filter's largest amplification
     // (the prediction cancels below that level) so that no column is blown up
@@ -790,29 +810,33 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
     small[SL::MZ + i * KMAX + c] = sv;
     small[SL::MB + i * KMAX + c] = -fc * sv;
   }
-  if (tid == 0) {
-    double mr = 0.0;
+  if (tid < 64) {
+    // wave 0, lane c = column c
+    const int c = tid;
     const int rk = r < k ? r : k;
-    int npos = 0;
-    while (npos < rk && vals[npos] > 0.0) ++npos;
+    // leading positive values among the r kept (values sorted decreasingly)
+    const unsigned long long stop = __ballot(c < rk && !(vals[c < k ? c : 0] > 0.0));
+    const int npos = stop ? (__ffsll((long long)stop) - 1) : rk;
     const int nchk = npos > 0 ? npos : (rk > 0 ? 1 : 0);
-    for (int c = 0; c < nchk; ++c) mr = fmax(mr, res[c]);
-    for (int c = 0; c < rk; ++c) small[lam_off + c] = fmax(vals[c], 0.0);
-    double* sc = small + SL::SC;
-    sc[S_MAXRES] = mr;
-    sc[S_LAMR] = vals[rk - 1];
-    sc[S_LAMR1] = (rk < k) ? vals[rk] : __builtin_nan("");
-    sc[S_NORMW] = scale;
-    sc[S_CHOLFIX] = (double)flag[0];
-    sc[S_FILTC] = fc;
-    sc[S_FILTE] = fe;
-    sc[S_SWEEPS] = (double)sweeps;
-    sc[S_RRPATH] = (double)path;
-    sc[S_RRCHOL] += (path < 0) ? 1.0 : 0.0;
-    sc[S_RRCOUNT] += 1.0;
-    bool bad = false;
-    for (int c = 0; c < k; ++c) bad |= !isfinite(vals[c]);
-    if (bad) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 1.0);
+    double mr = (c < nchk) ? resc : 0.0;
+    for (int o = 32; o > 0; o >>= 1) mr = fmax(mr, __shfl_xor(mr, o));
+    if (c < rk) small[lam_off + c] = fmax(vals[c], 0.0);
+    const bool bad = __ballot(c < k && !isfinite(vals[c < k ? c : 0])) != 0ull;
+    if (c == 0) {
+      double* sc = small + SL::SC;
+      sc[S_MAXRES] = mr;
+      sc[S_LAMR] = vals[rk - 1];
+      sc[S_LAMR1] = (rk < k) ? vals[rk] : __builtin_nan("");
+      sc[S_NORMW] = scale;
+      sc[S_CHOLFIX] = (double)flag[0];
+      sc[S_FILTC] = fc;
+      sc[S_FILTE] = fe;
+      sc[S_SWEEPS] = (double)sweeps;
+      sc[S_RRPATH] = (double)path;
+      sc[S_RRCHOL] += (path < 0) ? 1.0 : 0.0;
+      sc[S_RRCOUNT] += 1.0;
+      if (bad) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 1.0);
+    }
   }
 }
 #undef RR_FOR_KK
