@@ -171,6 +171,117 @@ __device__ __forceinline__ int jacobi_eig(double* A, int lda, double* U, int ldu
   return sweeps;
 }
 
+// Rotation of the 2 x 2 symmetric Schur decomposition for (app, apq; apq, aqq)
+// (Golub and Van Loan, Algorithm 8.4.1); c = 1, s = 0 below the negligible
+// level.
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double& c,
+                                                double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (fabs(apq) > 1e-18 * sqrt(fabs(app * aqq)) + 1e-300) {
+    const double th = (aqq - app) / (2.0 * apq);
+    const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+    c = 1.0 / sqrt(t * t + 1.0);
+    s = t * c;
+  }
+}
+
+// Cyclic Jacobi as jacobi_eig without threshold (same orderings, rotations
+// and stopping rule, k even), with A alternating between two LDS buffers A0
+// and A1: each round reads one and writes the other, and every thread forms
+// the rotations it applies from the round's input, so a round needs one
+// barrier.  Thread (bi, g) applies the rotation of row pair bi to the 2 x 2
+// blocks (bi, bj) for bj = g, g + groups, ... and to rows g, g + groups, ...
+// of U.  Returns the number of sweeps; *out is the buffer holding the result.
+__device__ __forceinline__ int jacobi_eig_db(double* A0, double* A1, int lda, double* U, int ldu,
+                                             int k, int max_sweeps, double tol_off, double* red,
+                                             double** out) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int t = tid; t < (k << 6); t += nt) {
+    const int i = t >> 6, j = t & 63;
+    if (j < k) U[i * ldu + j] = (i == j) ? 1.0 : 0.0;
+  }
+  const int np = k / 2, km1 = k - 1;
+  const int groups = nt / np;
+  const int bi = tid % np, g0 = tid / np;
+  const int nw = nt >> 6;
+  double* Ain = A0;
+  double* Aout = A1;
+  auto player = [&](int pos, int rnd) {
+    if (pos == 0) return 0;
+    int v = pos - 1 + rnd;
+    if (v >= km1) v -= km1;
+    return v + 1;
+  };
+  int sweeps = 0;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    __syncthreads();
+    double off = 0.0, dg = 0.0;
+    for (int t = tid; t < (k << 6); t += nt) {
+      const int i = t >> 6, j = t & 63;
+      if (j >= k) continue;
+      const double v = Ain[i * lda + j];
+      if (i == j)
+        dg += v * v;
+      else
+        off += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      dg += __shfl_xor(dg, o);
+    }
+    if ((tid & 63) == 0) {
+      red[2 * (tid >> 6)] = off;
+      red[2 * (tid >> 6) + 1] = dg;
+    }
+    __syncthreads();
+    off = 0.0;
+    dg = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      off += red[2 * w];
+      dg += red[2 * w + 1];
+    }
+    if (!(off > tol_off * tol_off * dg) || !(off > 1e-300)) break;
+    for (int rnd = 0; rnd < km1; ++rnd) {
+      if (g0 < groups) {
+        int pi = player(bi, rnd), qi = player(k - 1 - bi, rnd);
+        if (pi > qi) { const int t = pi; pi = qi; qi = t; }
+        double ci, si;
+        jacobi_rotation(Ain[pi * lda + pi], Ain[qi * lda + qi], Ain[pi * lda + qi], ci, si);
+        for (int bj = g0; bj < np; bj += groups) {
+          int pj = player(bj, rnd), qj = player(k - 1 - bj, rnd);
+          if (pj > qj) { const int t = pj; pj = qj; qj = t; }
+          double cj, sj;
+          jacobi_rotation(Ain[pj * lda + pj], Ain[qj * lda + qj], Ain[pj * lda + qj], cj, sj);
+          const double a = Ain[pi * lda + pj], b = Ain[pi * lda + qj];
+          const double c_ = Ain[qi * lda + pj], d = Ain[qi * lda + qj];
+          const double a1 = ci * a - si * c_, b1 = ci * b - si * d;
+          const double c1 = si * a + ci * c_, d1 = si * b + ci * d;
+          Aout[pi * lda + pj] = cj * a1 - sj * b1;
+          Aout[pi * lda + qj] = sj * a1 + cj * b1;
+          Aout[qi * lda + pj] = cj * c1 - sj * d1;
+          Aout[qi * lda + qj] = sj * c1 + cj * d1;
+        }
+        if (si != 0.0) {
+          for (int r0 = g0; r0 < k; r0 += groups) {
+            const double up = U[r0 * ldu + pi], uq = U[r0 * ldu + qi];
+            U[r0 * ldu + pi] = ci * up - si * uq;
+            U[r0 * ldu + qi] = si * up + ci * uq;
+          }
+        }
+      }
+      __syncthreads();
+      double* t = Ain;
+      Ain = Aout;
+      Aout = t;
+    }
+    ++sweeps;
+  }
+  __syncthreads();
+  *out = Ain;
+  return sweeps;
+}
+
 // Sorts eigenvalues (diagonal of A) decreasingly: writes values to `vals`
 // and the permutation to `perm`.  Rank sort: thread i counts the entries that
 // precede it (larger, or equal with a smaller index), k <= KMAX.
@@ -723,9 +834,12 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
   __syncthreads();
   // eigendecomposition of the projected matrix (B1, nearly diagonal on the
   // Newton path), eigenvectors in B2
-  sweeps = jacobi_eig(B1, ld, B2, ld, k, cs, flag + 1, 40, jac_tol, newton_ok,
-                      newton_ok ? imp : nullptr);
-  sort_desc(B1, ld, k, vals, perm);
+  double* Aeig = B1;
+  if (newton_ok)
+    sweeps = jacobi_eig(B1, ld, B2, ld, k, cs, flag + 1, 40, jac_tol, true, imp);
+  else   // B3 (free on this path) is the second buffer
+    sweeps = jacobi_eig_db(B1, B3, ld, B2, ld, k, 40, jac_tol, red, &Aeig);
+  sort_desc(Aeig, ld, k, vals, perm);
   if (newton_ok) {
     // coefficients D X U[:, perm] into B0 (X^T G X is no longer needed)
     strip_mm(B0, ld, B3, ld, B2, ld, perm, d, k);
