@@ -28,8 +28,8 @@ PEAK_FP64_TFLOPS = 78.6      # dense FP64 MFMA
 # HBM bytes per launch of the k = 64 dense pass from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, calibrated against a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0); see profiles/k_block_partial_f64_k_write_w_n5000_k64_hbm_counters.md.
-# Must be re-measured whenever k_block_partial_f64 changes.
-PASS_K64_TRAFFIC_BYTES = {"read": 226.6e6, "write": 18.1e6}
+# Must be re-measured whenever k_block_partial_f64 or its chunking changes.
+PASS_K64_TRAFFIC_BYTES = {"read": 227.8e6, "write": 23.3e6}
 
 
 def log(*a):
@@ -197,7 +197,7 @@ def main():
     roofline.update({
         "traffic": (PASS_K64_TRAFFIC_BYTES["read"] + PASS_K64_TRAFFIC_BYTES["write"]
                     if (n == 5000 and args.workload == "maxcut" and args.precision == "fp64") else None),
-        "traffic_note": "HBM bytes per k=64 launch (read 226.6 MB + write 18.1 MB of split-K "
+        "traffic_note": "HBM bytes per k=64 launch (read 227.8 MB + write 23.3 MB of split-K "
                         "partials, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated) vs 204.5 MB "
                         "algorithmic read",
         "kernel": "k_block_partial_f64 (dense pass W B, FP64 MFMA)",
