@@ -166,7 +166,9 @@ int proxsdp_workspace_size(const proxsdp_problem *prob, const proxsdp_options *o
  * d_workspace (device memory of at least proxsdp_workspace_size bytes,
  * 256-byte aligned) and sets X0 = 0, y0 = 0.  The workspace must stay valid
  * and untouched until proxsdp_destroy.  Enqueues on `stream` and
- * synchronises it before returning. */
+ * synchronises it before returning.  Besides the caller's device workspace
+ * the handle owns a pinned host buffer of check_every + 1 iteration records
+ * (the control checks' copy target), freed by proxsdp_destroy. */
 int proxsdp_create(const proxsdp_problem *prob, const proxsdp_options *opt, void *d_workspace,
                    size_t ws_bytes, void *stream, proxsdp_handle **out);
 

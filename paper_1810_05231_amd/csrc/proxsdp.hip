@@ -492,7 +492,12 @@ struct proxsdp_handle {
   std::vector<int> prof_k, prof_r;             // subspace width / rank of each timed launch
   int n_pass = 0, n_write = 0;
   hipEvent_t round_ev = nullptr;   // end of the last round launched by step_many
+  // pinned host copy of a control check's records (+ the non-finite flag), so
+  // that the check's device-to-host copy is a plain DMA
+  IterRecord* host_rec = nullptr;
+  int host_rec_cap = 0;
   ~proxsdp_handle() {
+    if (host_rec) (void)hipHostFree(host_rec);
     if (round_ev) (void)hipEventDestroy(round_ev);
     for (auto& kv : graphs) {
       if (kv.second.ex) (void)hipGraphExecDestroy(kv.second.ex);
@@ -1134,13 +1139,31 @@ static int confirm_lambda_r(proxsdp_handle* H, double* lam_r) {
 // Control check after iteration H->iters (a multiple of check_every).
 static int control(proxsdp_handle* H) {
   const int ce = H->opt.check_every;
-  std::vector<IterRecord> recs;
-  int rc = read_records(H, H->iters - ce, ce, recs);
-  if (rc) return rc;
-  double nonfinite = 0;
-  HIP_OK(hipMemcpyAsync(&nonfinite, H->small + SL::SC + S_NONFINITE, sizeof(double),
+  if (H->host_rec_cap < ce + 1) {
+    if (H->host_rec) HIP_OK(hipHostFree(H->host_rec));
+    H->host_rec = nullptr;
+    H->host_rec_cap = 0;
+    HIP_OK(hipHostMalloc((void**)&H->host_rec, (size_t)(ce + 1) * sizeof(IterRecord), hipHostMallocDefault));
+    H->host_rec_cap = ce + 1;
+  }
+  {
+    int done = 0;
+    const int first = H->iters - ce;
+    while (done < ce) {
+      const int slot = ((first + done) % RING + RING) % RING;
+      const int len = std::min(ce - done, RING - slot);
+      HIP_OK(hipMemcpyAsync(H->host_rec + done, H->ring + slot, len * sizeof(IterRecord),
+                            hipMemcpyDeviceToHost, H->st));
+      done += len;
+    }
+  }
+  double* nf_host = reinterpret_cast<double*>(H->host_rec + ce);
+  HIP_OK(hipMemcpyAsync(nf_host, H->small + SL::SC + S_NONFINITE, sizeof(double),
                         hipMemcpyDeviceToHost, H->st));
   HIP_OK(hipStreamSynchronize(H->st));
+  const std::vector<IterRecord> recs(H->host_rec, H->host_rec + ce);
+  const double nonfinite = *nf_host;
+  int rc = 0;
   const IterRecord& rec = recs.back();
   const double rho_p = rec.eps_p / (1.0 + H->h.norm_c);
   const double rho_d = rec.eps_d / (1.0 + H->h.norm_rhs);
@@ -1351,6 +1374,13 @@ int proxsdp_create(const proxsdp_problem* pb, const proxsdp_options* opt, void* 
   UP(d.tile_ptr, h.tile_ptr); UP(d.tile_item, h.tile_item); UP(d.tile_e, h.tile_e);
   UP(d.r1_u, h.r1_u); UP(d.row_r1, h.row_r1); UP(d.rhs, h.rhs);
 #undef UP
+  if (hipHostMalloc((void**)&H->host_rec, (size_t)(H->opt.check_every + 1) * sizeof(IterRecord),
+                    hipHostMallocDefault) != hipSuccess) {
+    H->host_rec = nullptr;
+    delete H;
+    return fail(PROXSDP_ERR_HIP, "pinned host buffer for the control checks");
+  }
+  H->host_rec_cap = H->opt.check_every + 1;
   if ((rc = init_state(H))) { delete H; return rc; }
   H->ws_need = need;
   H->status = PROXSDP_STATUS_RUNNING;

@@ -13,6 +13,11 @@ slot and memory go to waiting requests at once.
 
 Only orchestration lives here (arrival clock, admission, bookkeeping); every
 iteration runs in libproxsdp.
+
+HIP maps streams onto a small number of hardware queues (4 unless
+GPU_MAX_HW_QUEUES says otherwise); streams that share a queue run one after
+the other, so a process that serves many slots should export
+GPU_MAX_HW_QUEUES (e.g. 16, one queue per slot) before HIP initialises.
 """
 from __future__ import annotations
 
