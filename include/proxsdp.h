@@ -206,6 +206,27 @@ int proxsdp_get_solution(proxsdp_handle *h, double *X, double *y, int32_t on_dev
  * lambda has r values (>= 0).  Host pointers; either may be NULL.  *r_out gets r. */
 int proxsdp_get_factors(proxsdp_handle *h, double *V, double *lambda, int32_t *r_out);
 
+/* Resumable state in one call: the factors of X (as proxsdp_get_factors) and
+ * the dual y (m + p values, unscaled, as proxsdp_get_solution).  Host
+ * pointers; any may be NULL (call once with NULLs to learn r).  Synchronises.
+ * Algorithm 2 keeps its intermediate (X, y) in memory; this is the way to
+ * take it out for a later warm start. */
+int proxsdp_get_state(proxsdp_handle *h, double *V, double *lambda, double *y, int32_t *r_out);
+
+/* Warm start: restarts the iteration (counters, rank control and history
+ * cleared, as proxsdp_reset) from X0 = V diag(lambda) V^T and y0 instead of
+ * X0 = 0, y0 = 0 (Algorithm 1 from a given point).  V: n x r row-major host
+ * array (columns need not be orthonormal), lambda: r values, finite and
+ * >= 0 (X0 must be PSD), y: m + p values in the problem's own (unscaled)
+ * units and Section 1.3 sign, inequality duals <= 0, or NULL for y0 = 0.
+ * 0 <= r <= min(64, r cap) (n on the exact path).  The working rank becomes
+ * max(r0, r) (within the cap); the first Ritz basis starts from V's columns.
+ * Copies the arrays; synchronises `stream` of the handle.  Errors:
+ * PROXSDP_ERR_INVALID (bad r, NULL arrays for r > 0, negative or non-finite
+ * lambda, non-finite V or y, a positive inequality dual), PROXSDP_ERR_HIP. */
+int proxsdp_set_state(proxsdp_handle *h, int32_t r, const double *V, const double *lambda,
+                      const double *y);
+
 /* Restarts the iteration from X0 = 0, y0 = 0 (Algorithm 2 with r = r0) on the
  * problem data already on the device; no host transfer of problem data.
  * Synchronises the stream. */

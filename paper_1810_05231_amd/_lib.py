@@ -85,6 +85,8 @@ def _load():
         "proxsdp_solve": (C.c_int, [H, C.POINTER(Info)]),
         "proxsdp_get_solution": (C.c_int, [H, C.c_void_p, C.c_void_p, C.c_int32]),
         "proxsdp_get_factors": (C.c_int, [H, _f64p, _f64p, _i32p]),
+        "proxsdp_get_state": (C.c_int, [H, _f64p, _f64p, _f64p, _i32p]),
+        "proxsdp_set_state": (C.c_int, [H, C.c_int32, _f64p, _f64p, _f64p]),
         "proxsdp_destroy": (None, [H]),
         "proxsdp_project_workspace_size": (C.c_int, [C.c_int32, C.c_int32, C.c_int32,
                                                      C.POINTER(C.c_size_t)]),

@@ -792,7 +792,7 @@ static void launch_block_lowp(proxsdp_handle* H, const double* B, double* part) 
 static void launch_implicit(proxsdp_handle* H, const double* B, double* Z, bool grams = true) {
   hipStream_t st = H->st;
   const int pp = 1 - (H->iters & 1);       // factors of the current X
-  const int r = H->iters > 0 ? H->r_old : 0;
+  const int r = H->r_old;
   const int k = H->k;
   hipLaunchKernelGGL(k_vtb, dim3(H->nsl), dim3(256), 0, st, H->V[pp], r, B, k, H->dp.n_r1,
                      H->dp.r1_u, H->npad, H->vb_part);
@@ -813,7 +813,7 @@ static void launch_implicit(proxsdp_handle* H, const double* B, double* Z, bool 
 static void ensure_w_fresh(proxsdp_handle* H) {
   if (H->prec == PROXSDP_FP64 || H->w_fresh) return;
   const int pp = 1 - (H->iters & 1);
-  const int r = H->iters > 0 ? H->r_old : 0;
+  const int r = H->r_old;
   prof_mark(H, H->ev_write, H->n_write, true);
   launch_write(H, H->Wl, H->prec, H->npad, H->V[pp], r, lam_slot(pp), true, true, nullptr);
   prof_mark(H, H->ev_write, H->n_write, false);
@@ -1219,13 +1219,15 @@ static int control(proxsdp_handle* H) {
   return PROXSDP_OK;
 }
 
-static int warm_start(proxsdp_handle* H) {
-  // subspace for the first projection: random basis, rounds until the kept
-  // Ritz pairs are accurate to 1e-3 (relative) or 60 rounds.
+static int warm_start(proxsdp_handle* H, const double* src = nullptr, int nsrc = 0) {
+  // subspace for the first projection: the first nsrc columns from src
+  // (factor layout, row stride KMAX), the others random; rounds until the
+  // kept Ritz pairs are accurate to 1e-3 (relative) or 60 rounds.
   if (H->full) return PROXSDP_OK;
   const int64_t cnt = (int64_t)H->npad * H->k;
   hipLaunchKernelGGL(k_fill_basis, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, H->st,
-                     H->B[H->bcur], H->k, nullptr, 0, 0, H->n, H->npad, (uint32_t)H->opt.seed);
+                     H->B[H->bcur], H->k, src, KMAX, src ? std::min(nsrc, H->k) : 0, H->n, H->npad,
+                     (uint32_t)H->opt.seed);
   for (int rd = 0; rd < 60; ++rd) {
     eig_round(H, 0, false);
     if (rd % 4 == 3) {
@@ -1238,9 +1240,10 @@ static int warm_start(proxsdp_handle* H) {
   return PROXSDP_OK;
 }
 
-static int init_state(proxsdp_handle* H) {
+// Zeroes the iteration state (device buffers, scalars, control history) and
+// sets the working rank r0; X0 = 0, y0 = 0 until the caller writes more.
+static int reset_buffers(proxsdp_handle* H) {
   hipStream_t st = H->st;
-  // state: X0 = 0, y0 = 0
   if (H->prec == PROXSDP_FP64)
     zero(H->W, (size_t)H->npad * H->npad, st);
   else
@@ -1279,6 +1282,13 @@ static int init_state(proxsdp_handle* H) {
   H->r_old = 0;
   H->r = H->opt.full_eig ? H->n : std::min(std::max(H->opt.r0, 1), H->r_cap);
   H->k = H->full ? 16 : (H->opt.block ? H->opt.block : k_for_r(H->r));
+  return PROXSDP_OK;
+}
+
+static int init_state(proxsdp_handle* H) {
+  hipStream_t st = H->st;
+  int rc = reset_buffers(H);
+  if (rc) return rc;
   // W0 = X0 - alpha (C - M*(y0)) = -alpha C
   const int r_save = H->r;
   H->r = 0;
@@ -1287,7 +1297,7 @@ static int init_state(proxsdp_handle* H) {
   const double zero_flag = 0.0;
   HIP_OK(hipMemcpyAsync(H->small + SL::SC + S_NONFINITE, &zero_flag, sizeof(double),
                         hipMemcpyHostToDevice, st));
-  int rc = warm_start(H);
+  rc = warm_start(H);
   if (rc) return rc;
   HIP_OK(hipStreamSynchronize(st));
   return PROXSDP_OK;
@@ -1537,9 +1547,9 @@ int proxsdp_get_factors(proxsdp_handle* H, double* V, double* lambda, int32_t* r
   g_err.clear();
   if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
   const int par = (H->iters - 1) & 1;
-  const int r = H->iters > 0 ? H->r_old : 0;
+  const int r = H->r_old;
   if (r_out) *r_out = r;
-  if (H->iters == 0) return PROXSDP_OK;
+  if (r == 0) return PROXSDP_OK;
   if (V) {
     std::vector<double> tmp((size_t)H->n * KMAX);
     HIP_OK(hipMemcpyAsync(tmp.data(), H->V[par], tmp.size() * sizeof(double), hipMemcpyDeviceToHost, H->st));
@@ -1551,6 +1561,103 @@ int proxsdp_get_factors(proxsdp_handle* H, double* V, double* lambda, int32_t* r
     HIP_OK(hipMemcpyAsync(lambda, H->small + lam_slot(par), r * sizeof(double), hipMemcpyDeviceToHost, H->st));
     HIP_OK(hipStreamSynchronize(H->st));
   }
+  return PROXSDP_OK;
+}
+
+int proxsdp_set_state(proxsdp_handle* H, int32_t r, const double* V, const double* lambda,
+                      const double* y) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  const int n = H->n;
+  const Host& h = H->h;
+  const int rmax = std::min(H->opt.full_eig ? n : H->r_cap, KMAX);
+  if (r < 0 || r > rmax)
+    return fail(PROXSDP_ERR_INVALID, "r must be in [0, " + std::to_string(rmax) + "]");
+  if (r > 0 && (!V || !lambda)) return fail(PROXSDP_ERR_INVALID, "V and lambda are required for r > 0");
+  for (int t = 0; t < r; ++t)
+    if (!(lambda[t] >= 0.0) || !std::isfinite(lambda[t]))
+      return fail(PROXSDP_ERR_INVALID, "lambda must be finite and >= 0 (X is PSD)");
+  for (size_t t = 0; t < (size_t)n * r; ++t)
+    if (!std::isfinite(V[t])) return fail(PROXSDP_ERR_INVALID, "V has a non-finite entry");
+  if (y)
+    for (int i = 0; i < H->rows; ++i) {
+      if (!std::isfinite(y[i])) return fail(PROXSDP_ERR_INVALID, "y has a non-finite entry");
+      if (i >= h.m && y[i] > 0.0)
+        return fail(PROXSDP_ERR_INVALID, "inequality duals must be <= 0 (Section 1.3 sign)");
+    }
+  int rc = reset_buffers(H);
+  if (rc) return rc;
+  hipStream_t st = H->st;
+  // factors of X0 into the slot of iteration -1 (parity 1)
+  std::vector<double> Vp((size_t)H->npad * KMAX, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int t = 0; t < r; ++t) Vp[(size_t)i * KMAX + t] = V[(size_t)i * r + t];
+  std::vector<double> lam(r);
+  for (int t = 0; t < r; ++t) lam[t] = lambda[t];
+  // y0 in the scaled rows, M(X0) (the dual step's previous M(X)), ||X0||_F^2
+  std::vector<double> ys(H->rows, 0.0), mx(H->rows, 0.0);
+  for (int i = 0; i < H->rows; ++i) ys[i] = y ? y[i] * h.scale[i] : 0.0;
+  auto xab = [&](int a, int b) {
+    double acc = 0.0;
+    for (int t = 0; t < r; ++t) acc += lam[t] * V[(size_t)a * r + t] * V[(size_t)b * r + t];
+    return acc;
+  };
+  std::vector<double> uv((size_t)std::max(h.n_r1, 1) * std::max(r, 1), 0.0);
+  for (int q = 0; q < h.n_r1; ++q)
+    for (int t = 0; t < r; ++t) {
+      double acc = 0.0;
+      for (int i = 0; i < n; ++i) acc += h.r1_u[(size_t)q * h.npad + i] * V[(size_t)i * r + t];
+      uv[(size_t)q * r + t] = acc;
+    }
+  for (int i = 0; i < H->rows; ++i) {
+    double acc = 0.0;
+    for (int e = h.row_ptr[i]; e < h.row_ptr[i + 1]; ++e) acc += h.row_w[e] * xab(h.row_a[e], h.row_b[e]);
+    const int q = h.row_r1[i];
+    if (q >= 0) {
+      double a1 = 0.0;
+      for (int t = 0; t < r; ++t) a1 += lam[t] * uv[(size_t)q * r + t] * uv[(size_t)q * r + t];
+      acc += h.r1_sigma[q] * a1;
+    }
+    mx[i] = acc;
+  }
+  double sc2[2] = {0.0, 0.0};   // ||X0||_F^2, cleared non-finite flag
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < r; ++b) {
+      double g = 0.0;
+      for (int i = 0; i < n; ++i) g += V[(size_t)i * r + a] * V[(size_t)i * r + b];
+      sc2[0] += lam[a] * lam[b] * g * g;
+    }
+  HIP_OK(hipMemcpyAsync(H->V[1], Vp.data(), Vp.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  if (r > 0)
+    HIP_OK(hipMemcpyAsync(H->small + lam_slot(1), lam.data(), r * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(H->y, ys.data(), ys.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(H->y_old, ys.data(), ys.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(H->MX, mx.data(), mx.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(H->MX_old, mx.data(), mx.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  // W0 = X0 - alpha (C - M*(y0)) from the factors (its record is not used);
+  // the finalisation it runs overwrites ||X||^2 of parity 1, set afterwards
+  H->r_old = r;
+  const int r_work = H->r;
+  H->r = r;
+  pattern_and_write(H, 1, RING - 1);
+  H->r = H->opt.full_eig ? n : std::max(r_work, std::min(std::max(r, 1), H->r_cap));
+  H->k = H->full ? 16 : (H->opt.block ? H->opt.block : k_for_r(H->r));
+  HIP_OK(hipMemcpyAsync(H->small + SL::SC + S_X2 + 1, &sc2[0], sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(H->small + SL::SC + S_NONFINITE, &sc2[1], sizeof(double), hipMemcpyHostToDevice, st));
+  // Ritz basis: the given factors first
+  rc = warm_start(H, H->V[1], r);
+  if (rc) return rc;
+  HIP_OK(hipStreamSynchronize(st));   // the host buffers above end here
+  return PROXSDP_OK;
+}
+
+int proxsdp_get_state(proxsdp_handle* H, double* V, double* lambda, double* y, int32_t* r_out) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  int rc = proxsdp_get_factors(H, V, lambda, r_out);
+  if (rc) return rc;
+  if (y) return proxsdp_get_solution(H, nullptr, y, 0);
   return PROXSDP_OK;
 }
 
@@ -1570,7 +1677,7 @@ int proxsdp_get_solution(proxsdp_handle* H, double* X, double* y, int32_t on_dev
   }
   if (X) {
     const int par = (H->iters - 1) & 1;
-    const int r = H->iters > 0 ? H->r_old : 0;
+    const int r = H->r_old;
     if (on_device) {
       launch_write(H, X, PROXSDP_FP64, n, H->V[par], r, lam_slot(par), false, false, nullptr);
     } else {

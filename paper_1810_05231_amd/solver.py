@@ -144,6 +144,31 @@ class Solver:
               "get_factors")
         return V[:, :r.value], lam[:r.value]
 
+    def get_state(self):
+        """(V, lambda, y) of the current iterate (X = V diag(lambda) V^T, y unscaled)."""
+        r = C.c_int32()
+        check(lib.proxsdp_get_state(self._h, None, None, None, C.byref(r)), "get_state")
+        V = np.zeros((self.n, max(r.value, 1)))
+        lam = np.zeros(max(r.value, 1))
+        y = np.zeros(self.rows)
+        p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        check(lib.proxsdp_get_state(self._h, p(V), p(lam), p(y), C.byref(r)), "get_state")
+        return V[:, :r.value].copy(), lam[:r.value].copy(), y
+
+    def set_state(self, V, lam, y=None) -> None:
+        """Warm start from X0 = V diag(lam) V^T and y0 (unscaled; None = 0)."""
+        V = np.ascontiguousarray(V, dtype=np.float64).reshape(self.n, -1)
+        lam = np.ascontiguousarray(lam, dtype=np.float64).reshape(-1)
+        r = lam.size
+        if V.shape[1] != r:
+            raise ValueError("V must have one column per lambda")
+        p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        yy = None if y is None else np.ascontiguousarray(y, dtype=np.float64).reshape(-1)
+        if yy is not None and yy.size != self.rows:
+            raise ValueError(f"y must have {self.rows} values")
+        check(lib.proxsdp_set_state(self._h, r, p(V) if r else None, p(lam) if r else None,
+                                    p(yy) if yy is not None else None), "set_state")
+
     def reset(self) -> None:
         """Restart from X0 = 0, y0 = 0 on the data already on the device."""
         check(lib.proxsdp_reset(self._h), "proxsdp_reset")
