@@ -186,6 +186,45 @@ __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double a
   }
 }
 
+// FP64 reciprocal and reciprocal square root: the hardware estimates refined
+// by two Newton steps each (x <- x (2 - a x), y <- y (3 - a y^2) / 2).
+__device__ __forceinline__ double rcp_refined(double a) {
+  double x = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, x, 1.0);
+  x = fma(x, e, x);
+  e = fma(-a, x, 1.0);
+  return fma(x, e, x);
+}
+__device__ __forceinline__ double rsq_refined(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  double r = fma(-a * y, y, 1.0);
+  y = fma(0.5 * y, r, y);
+  r = fma(-a * y, y, 1.0);
+  return fma(0.5 * y, r, y);
+}
+
+// The rotation of jacobi_rotation (same tangent t = sign(d) e / (|d| +
+// sqrt(d^2 + e^2)), d = aqq - app, e = 2 apq, up to rounding) without IEEE
+// divisions or square roots: d and e are scaled by 1 / max(|d|, |e|) so that
+// d^2 + e^2 lies in [1, 2], and c = (1 + t^2)^(-1/2) is refined to full
+// precision, so c^2 + s^2 = 1 to rounding.
+__device__ __forceinline__ void jacobi_rotation_fast(double app, double aqq, double apq, double& c,
+                                                     double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (apq * apq > 1e-36 * fabs(app * aqq) && fabs(apq) > 1e-300) {
+    const double d = aqq - app, e = 2.0 * apq;
+    const double im = rcp_refined(fmax(fabs(d), fabs(e)));
+    const double dn = d * im, en = e * im;
+    const double q = fma(dn, dn, en * en);
+    const double hq = q * rsq_refined(q);
+    double t = en * rcp_refined(fabs(dn) + hq);
+    if (dn < 0.0) t = -t;
+    c = rsq_refined(fma(t, t, 1.0));
+    s = t * c;
+  }
+}
+
 // Cyclic Jacobi as jacobi_eig without threshold (same orderings, rotations
 // and stopping rule, k even), with A alternating between two LDS buffers A0
 // and A1: each round reads one and writes the other, and every thread forms
@@ -247,12 +286,12 @@ __device__ __forceinline__ int jacobi_eig_db(double* A0, double* A1, int lda, do
         int pi = player(bi, rnd), qi = player(k - 1 - bi, rnd);
         if (pi > qi) { const int t = pi; pi = qi; qi = t; }
         double ci, si;
-        jacobi_rotation(Ain[pi * lda + pi], Ain[qi * lda + qi], Ain[pi * lda + qi], ci, si);
+        jacobi_rotation_fast(Ain[pi * lda + pi], Ain[qi * lda + qi], Ain[pi * lda + qi], ci, si);
         for (int bj = g0; bj < np; bj += groups) {
           int pj = player(bj, rnd), qj = player(k - 1 - bj, rnd);
           if (pj > qj) { const int t = pj; pj = qj; qj = t; }
           double cj, sj;
-          jacobi_rotation(Ain[pj * lda + pj], Ain[qj * lda + qj], Ain[pj * lda + qj], cj, sj);
+          jacobi_rotation_fast(Ain[pj * lda + pj], Ain[qj * lda + qj], Ain[pj * lda + qj], cj, sj);
           const double a = Ain[pi * lda + pj], b = Ain[pi * lda + qj];
           const double c_ = Ain[qi * lda + pj], d = Ain[qi * lda + qj];
           const double a1 = ci * a - si * c_, b1 = ci * b - si * d;
