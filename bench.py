@@ -78,8 +78,8 @@ def main():
                     help="skip the FP32 precision-form solve reported beside the FP64 result")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the sweep would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the solver runs on a single device and has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import ctypes as C

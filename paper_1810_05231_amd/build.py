@@ -11,7 +11,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed FP32 instructions disabled on purpose
+    # packed FP32 instructions (v_pk_*_f32) are not generated: some of their
+    # forms have given wrong results on MI355X without any error
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-Wno-unused-parameter",
     "-I", os.path.join(ROOT, "include"),
