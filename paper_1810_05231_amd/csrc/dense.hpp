@@ -649,10 +649,14 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
   const int a0 = I * TILE, b0 = J * TILE;
   const int nq = rank1 ? dp.n_r1 : 0;
   const int rr = r + nq;
-  // LDS: first the scaled factor rows of the column block (64 x rr, row
-  // stride LDVB, rr <= KMAX + MAX_R1), staged once for the four waves with
-  // coalesced loads; then, in the same memory, the 64 x 64 output tile.
-  constexpr int LDVB = KMAX + MAX_R1 + 1;
+  // LDS: first the scaled factor rows of the column block (64 x rr, odd row
+  // stride rr + 1, rr <= KMAX + MAX_R1), staged once for the four waves with
+  // coalesced loads; then, in the same memory, the 64 x 64 output tile,
+  // unpadded with its columns permuted per row (element (a, c) at column
+  // c ^ a), so that both a row and a column of it are read without bank
+  // conflicts and the block needs 32 KB (five workgroups per CU) at rr < 64.
+  const int LDVB = rr + 1;
+  auto tix = [](int a, int c) { return a * TILE + (c ^ a); };
   double* sVb = sm;
   double* sT = sm;
   const double* lam = small + lam_off;
@@ -720,7 +724,7 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
     for (int nb = 0; nb < 4; ++nb) {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        sT[(16 * w + kq + 4 * v) * (TILE + 1) + 16 * nb + m] = acc[nb][v];
+        sT[tix(16 * w + kq + 4 * v, 16 * nb + m)] = acc[nb][v];
     }
   }
   if (sparse) {
@@ -728,7 +732,7 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
     const int t0 = dp.tile_ptr[tile_id], t1 = dp.tile_ptr[tile_id + 1];
     for (int t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
       const int it = dp.tile_item[t];
-      sT[(it >> 8) * (TILE + 1) + (it & 255)] += dval[dp.tile_e[t]];
+      sT[tix(it >> 8, it & 255)] += dval[dp.tile_e[t]];
     }
   }
   __syncthreads();
@@ -738,13 +742,13 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
   for (int q = 0; q < TILE / 4; ++q) {
     const int a = w + 4 * q;
     const int ga = a0 + a, gb = b0 + c;
-    if (ga < n && gb < n) W[(int64_t)ga * ld + gb] = store_cast<OutT>(sT[a * (TILE + 1) + c]);
+    if (ga < n && gb < n) W[(int64_t)ga * ld + gb] = store_cast<OutT>(sT[tix(a, c)]);
   }
   if (I != J) {
     for (int q = 0; q < TILE / 4; ++q) {
       const int b = w + 4 * q;
       const int gb = b0 + b, ga = a0 + c;
-      if (gb < n && ga < n) W[(int64_t)gb * ld + ga] = store_cast<OutT>(sT[c * (TILE + 1) + b]);
+      if (gb < n && ga < n) W[(int64_t)gb * ld + ga] = store_cast<OutT>(sT[tix(c, b)]);
     }
   }
 }

@@ -743,8 +743,9 @@ static void launch_write(proxsdp_handle* H, void* Wout, int out_prec, int64_t ld
                          int r, int lam_off, bool sparse, bool rank1, const FinArgs* fin,
                          bool tiles = true) {
   const int ts = H->npad / TILE;
-  // staged factor block (TILE x (KMAX + MAX_R1 + 1)), reused for the output tile
-  const size_t lds = (size_t)TILE * (KMAX + MAX_R1 + 1) * sizeof(double);
+  // staged factor block (TILE x (rr + 1)), reused for the TILE x TILE output tile
+  const int rr = r + (rank1 ? H->dp.n_r1 : 0);
+  const size_t lds = (size_t)TILE * std::max(rr + 1, TILE) * sizeof(double);
   FinArgs f{};
   if (fin) f = *fin;
   const dim3 grid((tiles ? ts * (ts + 1) / 2 : 0) + (fin ? 1 : 0));
