@@ -73,6 +73,11 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run paper_1810_05231_amd/build.py "
                            "(the HIP library is required, there is no fallback)")
+    # PyTorch ships its own HIP runtime; it has to be the one in the process
+    # before libproxsdp's HIP dependency is resolved, otherwise two runtimes
+    # get loaded and the second one finds no device.  Importing torch first
+    # makes the library bind to the runtime torch's tensors and streams live in.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     H = C.c_void_p
     sig = {

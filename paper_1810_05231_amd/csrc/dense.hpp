@@ -348,6 +348,9 @@ __global__ __launch_bounds__(512) void k_rowwise(const double* __restrict__ B,
   double* sZS = sV + SLICE * ldr;    // SLICE x ldr
   double* sU = sZS + SLICE * ldr;    // n_r1 x SLICE: rank-one vectors on the slice
   const int s = blockIdx.x;
+  // blockIdx.y == 1: the next basis only; blockIdx.y == 0: everything else
+  const bool part_bn = blockIdx.y == 1;
+  if (part_bn && !Bn) return;
   const int i0 = s * SLICE;
   const int64_t base = (int64_t)i0 * k;
   for (int t = threadIdx.x; t < SLICE * k; t += blockDim.x) {
@@ -355,7 +358,7 @@ __global__ __launch_bounds__(512) void k_rowwise(const double* __restrict__ B,
     sB[i * ldk + c] = B[base + t];
     sZ[i * ldk + c] = Z[base + t];
   }
-  if (V)
+  if (V && !part_bn)
     for (int t = threadIdx.x; t < n_r1 * SLICE; t += blockDim.x)
       sU[t] = r1_u[(int64_t)(t / SLICE) * npad + i0 + (t % SLICE)];
   __syncthreads();
@@ -366,7 +369,7 @@ __global__ __launch_bounds__(512) void k_rowwise(const double* __restrict__ B,
   const int m = lane & 15, kq = lane >> 4;
   const int rb = rp / 16, kb = k / 16;
   // jobs: [Vs blocks: 4 x rb] [ZS blocks: 4 x rb] [Bn blocks: 4 x kb]
-  const int nV = 4 * rb, nBn = Bn ? 4 * kb : 0;
+  const int nV = part_bn ? 0 : 4 * rb, nBn = part_bn ? 4 * kb : 0;
   for (int job = wave; job < 2 * nV + nBn; job += nw) {
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
     if (job < 2 * nV) {
@@ -393,6 +396,7 @@ __global__ __launch_bounds__(512) void k_rowwise(const double* __restrict__ B,
       }
     }
   }
+  if (part_bn) return;
   __syncthreads();
   double* out = fac_part + (int64_t)s * FAC_STRIDE;
   const double* theta = small + SL::THETA;

@@ -722,7 +722,7 @@ static void launch_rowwise(proxsdp_handle* H, const double* B, double* V, int r,
   const int rp = (r + 15) & ~15;
   const size_t lds = (2 * (size_t)SLICE * (H->k + 1) + 2 * (size_t)SLICE * (rp + 1) +
                       (size_t)MAX_R1 * SLICE) * sizeof(double);
-  hipLaunchKernelGGL(k_rowwise, dim3(H->nsl), dim3(512), lds, st, B, H->Z, H->small, H->k, V, r,
+  hipLaunchKernelGGL(k_rowwise, dim3(H->nsl, Bn ? 2 : 1), dim3(512), lds, st, B, H->Z, H->small, H->k, V, r,
                      Vold, r_old, Bn, H->dp.n_r1, H->dp.r1_u, H->npad, H->fac_part);
 }
 
