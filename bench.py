@@ -41,7 +41,10 @@ def main():
     # queues than HIP's default of 4 let more of them run concurrently (set
     # before HIP initialises; measured 1.2 -> 1.6 solves/s on 32 requests)
     if "--serving" in sys.argv or "--serving-only" in sys.argv:
-        os.environ["GPU_MAX_HW_QUEUES"] = "16"
+        slots = 16
+        if "--slots" in sys.argv:
+            slots = int(sys.argv[sys.argv.index("--slots") + 1])
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(max(slots, 4), 32))
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
