@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_block_partial_f64(
 typedef float f4 __attribute__((ext_vector_type(4)));
 template <int KB>
 __global__ __launch_bounds__(256) void k_block_partial_f32(
-    const float* __restrict__ W, int64_t ld, const double* __restrict__ B, int ldk,
+    const float* __restrict__ W, int64_t ld, const float* __restrict__ Bf, int ldk,
     double* __restrict__ part, int rows_per_chunk, int npad) {
   constexpr int K = KB * 16;
   constexpr int LDB = K + 1;
@@ -100,12 +100,20 @@ __global__ __launch_bounds__(256) void k_block_partial_f32(
     float w[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) w[u] = W[(int64_t)(j + 4 * u + lrow) * ld + col];
+    // the step's 64 x K basis block (FP32, contiguous): K / 16 float4 per thread
+    float4 bq[K / 16];
+#pragma unroll
+    for (int x = 0; x < K / 16; ++x)
+      bq[x] = reinterpret_cast<const float4*>(Bf + (int64_t)j * ldk)[threadIdx.x + 256 * x];
     __syncthreads();
 #pragma unroll
-    for (int t0 = 0; t0 < 64 * K; t0 += 256) {
-      const int t = t0 + threadIdx.x;
+    for (int x = 0; x < K / 16; ++x) {
+      const int t = 4 * (threadIdx.x + 256 * x);
       const int rr = t / K, cc = t - (t / K) * K;
-      sB[rr * LDB + cc] = (float)B[(int64_t)(j + rr) * ldk + cc];
+      sB[rr * LDB + cc] = bq[x].x;
+      sB[rr * LDB + cc + 1] = bq[x].y;
+      sB[rr * LDB + cc + 2] = bq[x].z;
+      sB[rr * LDB + cc + 3] = bq[x].w;
     }
     __syncthreads();
 #pragma unroll
@@ -170,7 +178,7 @@ __device__ __forceinline__ unsigned short store_cast<unsigned short>(double x) {
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 template <int KB>
 __global__ __launch_bounds__(256) void k_block_partial_bf16(
-    const unsigned short* __restrict__ W, int64_t ld, const double* __restrict__ B, int ldk,
+    const unsigned short* __restrict__ W, int64_t ld, const unsigned short* __restrict__ Bt, int ldk,
     double* __restrict__ part, int rows_per_chunk, int npad) {
   constexpr int K = KB * 16;
   constexpr int LDT = 64 + 8;   // staged row stride (bf16), 16-byte aligned rows
@@ -190,12 +198,21 @@ __global__ __launch_bounds__(256) void k_block_partial_bf16(
     uint4 wv[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) wv[h] = *reinterpret_cast<const uint4*>(wrow + j + 32 * h + 8 * q);
+    // the step's K x 64 block of the transposed BF16 basis: 8 pieces of 16
+    // bytes per basis column, K / 32 pieces per thread
+    constexpr int NP = (K * 8 + 255) / 256;
+    uint4 bp[NP];
+#pragma unroll
+    for (int x = 0; x < NP; ++x) {
+      const int c = threadIdx.x + 256 * x;
+      if (c < K * 8)
+        bp[x] = *reinterpret_cast<const uint4*>(Bt + (int64_t)(c >> 3) * npad + j + 8 * (c & 7));
+    }
     __syncthreads();
 #pragma unroll
-    for (int t0 = 0; t0 < 64 * K; t0 += 256) {
-      const int t = t0 + threadIdx.x;
-      const int jj = t / K, cc = t - (t / K) * K;
-      sBt[cc * LDT + jj] = to_bf16_rne(B[(int64_t)(j + jj) * ldk + cc]);
+    for (int x = 0; x < NP; ++x) {
+      const int c = threadIdx.x + 256 * x;
+      if (c < K * 8) *reinterpret_cast<uint4*>(&sBt[(c >> 3) * LDT + 8 * (c & 7)]) = bp[x];
     }
     __syncthreads();
 #pragma unroll
@@ -600,6 +617,31 @@ __global__ void k_fill_basis(double* __restrict__ B, int ldk, const double* __re
 __global__ void k_zero(double* __restrict__ x, int64_t count) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t < count) x[t] = 0.0;
+}
+
+// Low-precision copies of the basis block for the precision form's passes,
+// made once per pass (the pass workgroups then stage 2 or 4 bytes per entry
+// instead of converting 8-byte entries themselves):
+//   FP32: Bf[i][c] = (float) B[i][c]            (same layout, row stride k)
+//   BF16: Bt[c][i] = bf16_rne(B[i][c])          (transposed, row stride npad)
+__global__ __launch_bounds__(256) void k_basis_f32(const double* __restrict__ B, int64_t count,
+                                                   float* __restrict__ Bf) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < count) Bf[t] = (float)B[t];
+}
+__global__ __launch_bounds__(256) void k_basis_bf16t(const double* __restrict__ B, int k, int npad,
+                                                     unsigned short* __restrict__ Bt) {
+  __shared__ unsigned short s[64 * (KMAX + 2)];
+  const int i0 = blockIdx.x * 64;
+  for (int t = threadIdx.x; t < 64 * k; t += blockDim.x) {
+    const int ii = t / k, c = t - (t / k) * k;
+    s[ii * (KMAX + 2) + c] = to_bf16_rne(B[(int64_t)(i0 + ii) * k + c]);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 64 * k; t += blockDim.x) {
+    const int c = t >> 6, ii = t & 63;
+    Bt[(int64_t)c * npad + i0 + ii] = s[ii * (KMAX + 2) + c];
+  }
 }
 
 // Dense write, one workgroup per 64 x 64 tile (rows a0.., cols b0..):

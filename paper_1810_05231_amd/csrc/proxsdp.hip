@@ -452,6 +452,7 @@ struct proxsdp_handle {
   // device buffers
   int prec = PROXSDP_FP64;   // storage of W: FP64 (plain form), FP32 or BF16 (precision form)
   int wbytes = 8;            // bytes per stored element of W
+  float* Bl = nullptr;       // FP32 / BF16 copy of the basis block (precision form)
   double* W = nullptr;       // FP64 W (plain form and the exact small-n path)
   void* Wl = nullptr;        // FP32 / BF16 W (precision form)
   double* vb_part = nullptr; // per-slice partials of V^T B, u^T B (implicit operator)
@@ -533,6 +534,8 @@ static size_t carve(proxsdp_handle* H, void* ws) {
     H->W = nullptr;
     H->Wl = c.take<char>((size_t)npad * npad * H->wbytes);
   }
+  // low-precision copy of the basis block (precision form's dense passes)
+  H->Bl = H->prec == PROXSDP_FP64 ? nullptr : c.take<float>((size_t)npad * H->k_cap);
   H->vb_part = c.take<double>((size_t)std::max(H->nsl, 1) * VB_STRIDE);
   H->B[0] = c.take<double>((size_t)npad * H->k_cap);
   H->B[1] = c.take<double>((size_t)npad * H->k_cap);
@@ -766,9 +769,12 @@ static void launch_write(proxsdp_handle* H, void* Wout, int out_prec, int64_t ld
 // (FP32 storage: FP32 MFMA; summed in FP64 by the reduction).
 static void launch_block_lowp(proxsdp_handle* H, const double* B, double* part) {
   dim3 grid(H->npad / 64, H->ch.nchunks);
+  const int64_t cnt = (int64_t)H->npad * H->k;
   if (H->prec == PROXSDP_BF16) {
     const unsigned short* Wb = static_cast<const unsigned short*>(H->Wl);
-#define BB(KB) hipLaunchKernelGGL((k_block_partial_bf16<KB>), grid, dim3(256), 0, H->st, Wb, (int64_t)H->npad, B, H->k, part, H->ch.rows_per_chunk, H->npad)
+    unsigned short* Bt = reinterpret_cast<unsigned short*>(H->Bl);
+    hipLaunchKernelGGL(k_basis_bf16t, dim3(H->npad / 64), dim3(256), 0, H->st, B, H->k, H->npad, Bt);
+#define BB(KB) hipLaunchKernelGGL((k_block_partial_bf16<KB>), grid, dim3(256), 0, H->st, Wb, (int64_t)H->npad, Bt, H->k, part, H->ch.rows_per_chunk, H->npad)
     switch (H->k / 16) {
       case 1: BB(1); break;
       case 2: BB(2); break;
@@ -779,12 +785,15 @@ static void launch_block_lowp(proxsdp_handle* H, const double* B, double* part) 
     return;
   }
   const float* Wf = static_cast<const float*>(H->Wl);
+  hipLaunchKernelGGL(k_basis_f32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, H->st, B, cnt, H->Bl);
+#define BF(KB) hipLaunchKernelGGL((k_block_partial_f32<KB>), grid, dim3(256), 0, H->st, Wf, (int64_t)H->npad, H->Bl, H->k, part, H->ch.rows_per_chunk, H->npad)
   switch (H->k / 16) {
-    case 1: hipLaunchKernelGGL((k_block_partial_f32<1>), grid, dim3(256), 0, H->st, Wf, (int64_t)H->npad, B, H->k, part, H->ch.rows_per_chunk, H->npad); break;
-    case 2: hipLaunchKernelGGL((k_block_partial_f32<2>), grid, dim3(256), 0, H->st, Wf, (int64_t)H->npad, B, H->k, part, H->ch.rows_per_chunk, H->npad); break;
-    case 3: hipLaunchKernelGGL((k_block_partial_f32<3>), grid, dim3(256), 0, H->st, Wf, (int64_t)H->npad, B, H->k, part, H->ch.rows_per_chunk, H->npad); break;
-    default: hipLaunchKernelGGL((k_block_partial_f32<4>), grid, dim3(256), 0, H->st, Wf, (int64_t)H->npad, B, H->k, part, H->ch.rows_per_chunk, H->npad); break;
+    case 1: BF(1); break;
+    case 2: BF(2); break;
+    case 3: BF(3); break;
+    default: BF(4); break;
   }
+#undef BF
 }
 
 // Z = W B applied exactly in FP64 from the factors of the current X, the
