@@ -705,7 +705,7 @@ static void launch_reduce(const double* part, int nchunks, double* Z, const doub
 static void launch_rr(const double* gram_part, int nsl, double* small, int k, int r, int lam_off,
                       int filter, double jac_tol, hipStream_t st, int oa_steps = 10) {
   const int kk = k * k;
-  hipLaunchKernelGGL(k_sum_grams, dim3((3 * kk + 255) / 256), dim3(256), 0, st, gram_part, nsl, k,
+  hipLaunchKernelGGL(k_sum_grams, dim3((4 * 3 * kk + 255) / 256), dim3(256), 0, st, gram_part, nsl, k,
                      small);
   const size_t lds = small_rr_lds_doubles(k) * sizeof(double) + (2 * KMAX + 4) * sizeof(int);
 #define RR_LAUNCH(KQ)                                                                    \

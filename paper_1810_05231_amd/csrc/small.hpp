@@ -995,17 +995,24 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
 #undef RR_FOR_KK
 
 // Sums the per-slice Gram partials [B^T B, B^T Z, Z^T Z] into the GG/TG/PG
-// slots of `small` (one thread per entry, fixed summation order).
+// slots of `small`: four lanes per entry, each summing every fourth slice,
+// combined by a fixed butterfly (fixed summation order).
 __global__ __launch_bounds__(256) void k_sum_grams(const double* __restrict__ gram_part,
                                                    int nslices, int k, double* __restrict__ small) {
   const int kk = k * k;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * kk) return;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = g >> 2, part = g & 3;
   double acc = 0.0;
+  if (t < 3 * kk) {
 #pragma unroll 8
-  for (int s = 0; s < nslices; ++s) acc += gram_part[(int64_t)s * 3 * kk + t];
-  const int which = t / kk;
-  small[SL::GG + which * SL::kk + (t - which * kk)] = acc;
+    for (int s = part; s < nslices; s += 4) acc += gram_part[(int64_t)s * 3 * kk + t];
+  }
+  acc += __shfl_xor(acc, 1);
+  acc += __shfl_xor(acc, 2);
+  if (t < 3 * kk && part == 0) {
+    const int which = t / kk;
+    small[SL::GG + which * SL::kk + (t - which * kk)] = acc;
+  }
 }
 
 // Exact eigendecomposition of the n x n W (n <= KMAX) in one workgroup; the
