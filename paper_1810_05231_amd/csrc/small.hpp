@@ -171,21 +171,6 @@ __device__ __forceinline__ int jacobi_eig(double* A, int lda, double* U, int ldu
   return sweeps;
 }
 
-// Rotation of the 2 x 2 symmetric Schur decomposition for (app, apq; apq, aqq)
-// (Golub and Van Loan, Algorithm 8.4.1); c = 1, s = 0 below the negligible
-// level.
-__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double& c,
-                                                double& s) {
-  c = 1.0;
-  s = 0.0;
-  if (fabs(apq) > 1e-18 * sqrt(fabs(app * aqq)) + 1e-300) {
-    const double th = (aqq - app) / (2.0 * apq);
-    const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-    c = 1.0 / sqrt(t * t + 1.0);
-    s = t * c;
-  }
-}
-
 // FP64 reciprocal and reciprocal square root: the hardware estimates refined
 // by two Newton steps each (x <- x (2 - a x), y <- y (3 - a y^2) / 2).
 __device__ __forceinline__ double rcp_refined(double a) {
@@ -203,9 +188,11 @@ __device__ __forceinline__ double rsq_refined(double a) {
   return fma(0.5 * y, r, y);
 }
 
-// The rotation of jacobi_rotation (same tangent t = sign(d) e / (|d| +
-// sqrt(d^2 + e^2)), d = aqq - app, e = 2 apq, up to rounding) without IEEE
-// divisions or square roots: d and e are scaled by 1 / max(|d|, |e|) so that
+// Rotation of the 2 x 2 symmetric Schur decomposition of (app, apq; apq, aqq)
+// (Golub and Van Loan, Algorithm 8.4.1; the tangent of jacobi_eig's rotation,
+// t = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = aqq - app, e = 2 apq, up to
+// rounding; c = 1, s = 0 below the negligible level) without IEEE divisions
+// or square roots: d and e are scaled by 1 / max(|d|, |e|) so that
 // d^2 + e^2 lies in [1, 2], and c = (1 + t^2)^(-1/2) is refined to full
 // precision, so c^2 + s^2 = 1 to rounding.
 __device__ __forceinline__ void jacobi_rotation_fast(double app, double aqq, double apq, double& c,
