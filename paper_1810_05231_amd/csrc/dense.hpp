@@ -558,32 +558,51 @@ __global__ __launch_bounds__(256) void k_implicit_rows(DevProblem dp, const doub
                                                        const double* __restrict__ dval,
                                                        const double* __restrict__ B, int k,
                                                        double* __restrict__ Z) {
+  // one wave per row i (lane c = column c of Z); the row's pattern entries are
+  // fetched by the lanes together and broadcast one by one, so that their
+  // basis rows are read back to back instead of after a chain of index loads
   const int c = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= k || i >= dp.npad) return;
+  if (i >= dp.npad) return;   // whole waves
   double acc = 0.0;
   if (i < dp.n) {
-    const double* M = small + SL::VB;
-    const double* vrow = V + (int64_t)i * KMAX;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int t = 0;
-    for (; t + 3 < r; t += 4) {
-      a0 += vrow[t] * M[t * KMAX + c];
-      a1 += vrow[t + 1] * M[(t + 1) * KMAX + c];
-      a2 += vrow[t + 2] * M[(t + 2) * KMAX + c];
-      a3 += vrow[t + 3] * M[(t + 3) * KMAX + c];
+    if (c < k) {
+      const double* M = small + SL::VB;
+      const double* vrow = V + (int64_t)i * KMAX;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int t = 0;
+      for (; t + 3 < r; t += 4) {
+        a0 += vrow[t] * M[t * KMAX + c];
+        a1 += vrow[t + 1] * M[(t + 1) * KMAX + c];
+        a2 += vrow[t + 2] * M[(t + 2) * KMAX + c];
+        a3 += vrow[t + 3] * M[(t + 3) * KMAX + c];
+      }
+      for (; t < r; ++t) a0 += vrow[t] * M[t * KMAX + c];
+      acc = (a0 + a1) + (a2 + a3);
+      for (int q = 0; q < dp.n_r1; ++q)
+        acc += dp.r1_u[(int64_t)q * dp.npad + i] * M[KMAX * KMAX + q * KMAX + c];
     }
-    for (; t < r; ++t) a0 += vrow[t] * M[t * KMAX + c];
-    acc = (a0 + a1) + (a2 + a3);
-    for (int q = 0; q < dp.n_r1; ++q)
-      acc += dp.r1_u[(int64_t)q * dp.npad + i] * M[KMAX * KMAX + q * KMAX + c];
-    for (int e0 = dp.sym_ptr[i]; e0 < dp.sym_ptr[i + 1]; ++e0) {
-      const int e = dp.sym_e[e0];
-      const int ea = dp.pat_a[e], eb = dp.pat_b[e];
-      acc += dval[e] * B[(int64_t)((ea == i) ? eb : ea) * k + c];
+    const int s0 = dp.sym_ptr[i], s1 = dp.sym_ptr[i + 1];
+    for (int base = s0; base < s1; base += 64) {
+      const int s = base + c;
+      int other = 0;
+      double dv = 0.0;
+      if (s < s1) {
+        const int e = dp.sym_e[s];
+        const int ea = dp.pat_a[e], eb = dp.pat_b[e];
+        other = (ea == i) ? eb : ea;
+        dv = dval[e];
+      }
+      const int cnt = min(64, s1 - base);
+#pragma unroll 8
+      for (int j = 0; j < cnt; ++j) {
+        const int oj = __shfl(other, j);
+        const double dj = __shfl(dv, j);
+        if (c < k) acc += dj * B[(int64_t)oj * k + c];
+      }
     }
   }
-  Z[(int64_t)i * k + c] = acc;
+  if (c < k) Z[(int64_t)i * k + c] = acc;
 }
 
 // Fills rows < n of an npad x ldk block (columns [c0, c1)) with uniform(-1, 1)
