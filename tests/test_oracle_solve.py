@@ -137,6 +137,34 @@ def test_two_by_two_closed_form():
     assert np.allclose(res.X, [[1, -1], [-1, 1]], atol=1e-5)
 
 
+@pytest.mark.parametrize("kind,n", [("maxcut", 5), ("maxcut", 8), ("equip", 6)])
+def test_warm_start_at_the_optimum_is_a_fixed_point(kind, n):
+    # K_n: X* = n/(n-1) (I - 11^T/n) is optimal for both relaxations.  Max-cut:
+    # y* = -(n/4) 1, S* = C - M*(y*) = 11^T/4.  Equipartition (rank-one row
+    # <11^T, X> = 0): y* = (n 1, -1), S* = 0.  X* S* = 0, so one step of
+    # Algorithm 1 from (X*, y*) returns (X*, y*) and the solve started there
+    # stops at its first check.  y0 enters in the scaled rows (R2); the
+    # all-ones row has Frobenius norm n, so a scaling slip breaks the fixed
+    # point (an unscaled y0 runs 50 iterations and moves y by 0.14).
+    # (Pins the oracle's start from a given point, the reference of the
+    # library's warm start.)
+    if kind == "maxcut":
+        prob = I.from_edges_maxcut(n, I.complete_edges(n))
+        ys = -n / 4 * np.ones(n)
+        opt = -n * n / 4
+    else:
+        prob = I.from_edges_equipartition(n, I.complete_edges(n))
+        ys = np.concatenate([n * np.ones(n), [-1.0]])
+        opt = float(n * n)
+    Xs = n / (n - 1) * (np.eye(n) - np.ones((n, n)) / n)
+    ops = O.Operators(prob)
+    res = O.solve(prob, tol=1e-8, full_eig=True, X0=Xs, y0=ys * ops.scale, ops=ops)
+    assert res.iters == 10
+    assert np.abs(res.X - Xs).max() <= 1e-12
+    assert np.abs(res.y - ys).max() <= 1e-12 * max(1.0, np.abs(ys).max())
+    assert res.obj == pytest.approx(opt, rel=1e-13)
+
+
 def test_certificate_vanishes_at_known_optimum_only():
     n = 6
     prob = I.from_edges_maxcut(n, I.complete_edges(n))
