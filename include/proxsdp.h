@@ -31,8 +31,11 @@
  *  - Host arrays passed to a call are read during the call and copied; the
  *    caller may free them on return.
  *  - Device memory is the caller's: every call that needs device memory
- *    takes a workspace pointer and size.  The library never allocates or
- *    frees device memory and never frees the caller's memory.
+ *    takes a workspace pointer and size.  The library never frees the
+ *    caller's memory and allocates no device memory itself, with one
+ *    exception: the exact projection for n > 64 (proxsdp_project_psd, r = 0)
+ *    creates one rocBLAS handle per process on first use, which holds a small
+ *    allocation of its own (its work buffers come from the workspace).
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Work
  *    is enqueued on it; calls that return host results synchronise it.
  *  - A handle is not thread-safe; distinct handles are independent.
@@ -280,8 +283,9 @@ int proxsdp_project_workspace_size(int32_t n, int32_t r, int32_t precision, size
 
 /* aproj(S, r) of Section 3.1 (eq_trunc_eig): sum over the r algebraically
  * largest eigenvalues lambda_i of the symmetric S of max(0, lambda_i) u_i u_i^T;
- * r = 0 or r >= n gives the exact projection of Section 2.3.2 (n <= 64);
- * for n > 64 the target rank must be <= 48.
+ * r = 0 or r >= n gives the exact projection of Section 2.3.2 (one-workgroup
+ * Jacobi for n <= 64, rocSOLVER dsyevd and a rocBLAS product above); for
+ * 0 < r < n and n > 64 the target rank must be <= 48 (partial eigensolve).
  *   S       device, n x n row-major with leading dimension lds >= n, FP64
  *           (precision = PROXSDP_FP64); only read.  Must be symmetric.
  *   P       device, n x n output with leading dimension ldp, or NULL.
