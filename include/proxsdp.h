@@ -192,7 +192,9 @@ int proxsdp_solve(proxsdp_handle *h, proxsdp_info *info);
  * PROXSDP_STEP_UNTIL_ANY_STOPS the call returns once any handle stops
  * (converged, limits), after the rounds in flight have finished; handles that
  * did not finish their n_iters continue in the next call.  Handles on the same
- * stream are valid but run one after the other.  infos (host array of count
+ * stream are valid but run one after the other, and so do streams that HIP
+ * maps onto the same hardware queue (GPU_MAX_HW_QUEUES, 4 unless set before
+ * HIP initialises; measured best at one queue per stream, 16 streams).  infos (host array of count
  * entries, nullable) receives each handle's state.  Synchronises every stream
  * before returning.  Errors: PROXSDP_ERR_INVALID for a NULL entry or
  * n_iters < 0. */
