@@ -14,9 +14,15 @@ Parity status per function (pins live in tests/test_oracle_*.py):
   pdhg_step, solve                     pinned (closed-form optima of K_n, C_n,
                                        bipartite graphs; brute-force max-cut and
                                        bisection brackets; KKT at convergence)
+  residuals eps_p, eps_d (Sec. 2.2)    pinned (hand-derived one- and two-step
+                                       values on 1 x 1 equality / inequality rows)
+  rank test of Alg. 2                  pinned (odd cycles: rank-2 optimum, the
+                                       rank path must end 1 -> 2 -> 4)
   certificate                          pinned (vanishes at closed-form optima,
                                        positive at perturbed points)
-  maxcut_bracket                       pinned (brackets closed-form values)
+  maxcut_bracket                       pinned (exact values on K_n at the closed-
+                                       form optimum, rescaled and feasible points)
+  brute_force_maxcut / _min_bisection  pinned (K_n and C_n closed forms)
 """
 from .sdp import *  # noqa: F401,F403
 from .sdp import (CONVERGED, MAX_ITERS, NUMERICAL, TIME_LIMIT, Certificate, Operators,  # noqa
