@@ -25,7 +25,7 @@ Parity status per function (pins live in tests/test_oracle_*.py):
   brute_force_maxcut / _min_bisection  pinned (K_n and C_n closed forms)
 """
 from .sdp import *  # noqa: F401,F403
-from .sdp import (CONVERGED, MAX_ITERS, NUMERICAL, TIME_LIMIT, Certificate, Operators,  # noqa
+from .sdp import (CONVERGED, MAX_ITERS, NUMERICAL, RANK_LIMIT, TIME_LIMIT, Certificate, Operators,  # noqa
                   SolveResult, aproj_psd, brute_force_maxcut, brute_force_min_bisection,
                   certificate, dense_sym_from_coo, dual_resolvent, eig_desc, maxcut_bracket,
                   pdhg_step, proj_box, proj_psd, smat, solve, svec, svec_index)

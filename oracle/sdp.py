@@ -35,6 +35,15 @@ R5  X0 = 0, y0 = 0.
 R6  aproj takes the r algebraically largest eigenvalues (Section 3.1).
 R7  The truncation error identity of Section 3.1 is read with squares
     (Eckart-Young): ||proj - aproj||_F^2 = sum_{i>r} max(lambda_i, 0)^2.
+R8  Rank cap.  Algorithm 2 doubles r until, at worst, r = n.  With a cap
+    r_max < n the doubling is impossible once r = r_max: a converged iterate
+    that fails the rank test there stops with status RANK_LIMIT (it is the
+    feasible X_[r] of Section 3.2, not an optimum); a stalled window at the
+    cap keeps iterating.  r_max = n (the default) is Algorithm 2 itself.
+R9  Rank test variable.  The default is Algorithm 2's lambda_r (the r-th
+    largest eigenvalue of the projected matrix).  rank_test="lambda_r_plus_1"
+    uses the first excluded eigenvalue lambda_{r+1} instead (the quantity the
+    Section 3.1 error bound is really about); r = n passes either way.
 """
 from __future__ import annotations
 
@@ -48,9 +57,10 @@ import scipy.sparse.linalg as spla
 
 SQRT2 = math.sqrt(2.0)
 
-CONVERGED, MAX_ITERS, TIME_LIMIT, NUMERICAL = 0, 1, 2, 3
+CONVERGED, MAX_ITERS, TIME_LIMIT, NUMERICAL, RANK_LIMIT = 0, 1, 2, 3, 4
 STATUS_NAMES = {CONVERGED: "converged", MAX_ITERS: "max_iters",
-                TIME_LIMIT: "time_limit", NUMERICAL: "numerical"}
+                TIME_LIMIT: "time_limit", NUMERICAL: "numerical", RANK_LIMIT: "rank_limit"}
+RANK_TESTS = ("lambda_r", "lambda_r_plus_1")
 
 
 # ------------------------------------------------------------ svec geometry
@@ -270,7 +280,7 @@ class SolveResult:
     lam_r: float
     alpha: float
     rank_path: list = field(default_factory=list)
-    saved: list = field(default_factory=list)   # intermediate (r, X_[r], y_[r])
+    saved: list = field(default_factory=list)   # intermediate (iter, r, X_[r], y_[r]), y unscaled
     trace: list = field(default_factory=list)
     time_s: float = 0.0
 
@@ -279,12 +289,14 @@ def solve(prob, tol: float = 1e-4, r0: int = 1, full_eig: bool = False, window: 
           check_every: int = 10, max_iters: int = 100000, eps_lambda: float | None = None,
           alpha: float | None = None, row_scaling: bool = True, r_max: int | None = None,
           time_limit: float = float("inf"), X0=None, y0=None, keep_trace: bool = False,
-          ops: Operators | None = None) -> SolveResult:
+          ops: Operators | None = None, rank_test: str = "lambda_r") -> SolveResult:
     """LR-PD-SDP (Algorithm 2) with PD-SDP (Algorithm 1) as the r = n case.
 
-    Control per R3/R4; X0 = y0 = 0 unless given (R5).  ``y0`` is in the
-    scaled space of R2.
+    Control per R3/R4/R8/R9; X0 = y0 = 0 unless given (R5).  ``y0`` is in
+    the scaled space of R2.
     """
+    if rank_test not in RANK_TESTS:
+        raise ValueError(f"rank_test must be one of {RANK_TESTS}")
     t0 = time.perf_counter()
     if ops is None:
         ops = Operators(prob, row_scaling=row_scaling)
@@ -322,14 +334,18 @@ def solve(prob, tol: float = 1e-4, r0: int = 1, full_eig: bool = False, window: 
         if keep_trace:
             trace.append((k, r, rho_p, rho_d, float(lam_r)))
         if max(rho_p, rho_d) <= tol:
-            if r >= n or (n - r) * max(lam_r, 0.0) <= eps_lambda:
+            if rank_test == "lambda_r":
+                lam_test = lam_r
+            else:
+                lam_test = out.lam[r] if r < n else -math.inf
+            if r >= n or (n - r) * max(lam_test, 0.0) <= eps_lambda:
                 status = CONVERGED
                 break
-            saved.append((r, X.copy(), y.copy()))
+            saved.append((k, r, X.copy(), y / ops.scale))
             if r >= r_max:
-                # cannot raise the rank any further: keep iterating at r_max
-                hist.append(out.eps_p + out.eps_d)
-                continue
+                # the doubling of Algorithm 2 is impossible at the cap (R8)
+                status = RANK_LIMIT
+                break
             r = min(2 * r, r_max)
             rank_path.append((k, r))
             hist = []

@@ -151,3 +151,49 @@ def test_maxcut_bracket_closed_forms_on_complete_graph(n):
     assert lmin < 0
     assert lo5 == pytest.approx(-n * n / 4 + d + n * lmin, abs=1e-12)
     assert lo5 < -n * n / 4
+
+
+@pytest.mark.parametrize("n", [5, 7])
+def test_rank_test_lambda_r_plus_1_stops_at_the_rank(n):
+    # the first excluded eigenvalue lambda_3 of the projected matrix is <= 0 at
+    # the rank-2 optimum, so the lambda_{r+1} reading stops at r = 2
+    prob = I.from_edges_maxcut(n, I.cycle_edges(n))
+    res = O.solve(prob, tol=1e-8, rank_test="lambda_r_plus_1")
+    assert res.status == O.CONVERGED
+    assert [r for _, r in res.rank_path] == [1, 2]
+    assert -res.obj == pytest.approx(n / 2 * (1 + math.cos(math.pi / n)), rel=1e-6)
+
+
+@pytest.mark.parametrize("n", [5, 7])
+def test_rank_cap_stops_with_rank_limit(n):
+    # r_max = 2 < n: the residual converges at r = 2 but the lambda_r test fails
+    # (lambda_2 > 0 at a rank-2 optimum) and r cannot double: RANK_LIMIT.  The
+    # saved X_[r] are feasible (unit diagonal, PSD); X_[2] is in fact optimal
+    # here, which the literal lambda_r test cannot see.
+    prob = I.from_edges_maxcut(n, I.cycle_edges(n))
+    res = O.solve(prob, tol=1e-8, r_max=2)
+    assert res.status == O.RANK_LIMIT
+    assert res.r == 2
+    assert [s[1] for s in res.saved] == [1, 2]
+    for _, r, Xr, yr in res.saved:
+        assert np.allclose(np.diag(Xr), 1.0, atol=1e-6)
+        assert np.linalg.eigvalsh(Xr)[0] >= -1e-10
+        assert np.linalg.matrix_rank(Xr, tol=1e-6) <= r
+    assert -res.obj == pytest.approx(n / 2 * (1 + math.cos(math.pi / n)), rel=1e-6)
+    # X_[1] is a rank-one feasible point: +-1 vector outer product, so its cut
+    # value is an integer cut, at most the maximum cut (n - 1 for odd cycles)
+    X1 = res.saved[0][2]
+    L = np.zeros((n, n))
+    for a, b in I.cycle_edges(n):
+        L[a, a] += 1
+        L[b, b] += 1
+        L[a, b] -= 1
+        L[b, a] -= 1
+    cut1 = float(np.sum(-0.25 * L * X1))
+    assert -cut1 <= n - 1 + 1e-6
+
+
+def test_rank_test_option_is_checked():
+    prob = I.from_edges_maxcut(5, I.cycle_edges(5))
+    with pytest.raises(ValueError):
+        O.solve(prob, rank_test="lambda_max")
