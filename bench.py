@@ -7,6 +7,13 @@ device-side restart `proxsdp_reset` is inside the timed region; host
 preprocessing and the host-to-device upload happen once in `create`, outside
 it, and are reported as `setup_s`).
 
+The timed solves record no events; one further solve records HIP events on
+the library's stream around every dense pass and dense write, which give the
+roofline object.  The CPU leg times the oracle and, unless the workload is
+sensor localisation, certifies every GPU answer (FP64 and the precision
+forms) with the oracle: one exact FP64 PDHG step from it, and for max-cut the
+certified bracket on the optimal value.
+
 `--iters K` replaces the solve by K iterations (short runs for hardware
 counters); `--copy-calibration MIB` first runs a plain device copy of that
 size, whose counter readings calibrate the HBM byte counters.
@@ -166,20 +173,30 @@ def main():
             f"time={info['time_s']:.3f}s obj={info['obj']:.6f}")
     torch.cuda.synchronize()
     times, infos, profs = [], [], []
+    # timed solves: no profiling events on the stream
     for k in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        info, prof = one_solve(profile=True)
+        info, _ = one_solve(profile=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         times.append(dt)
         infos.append(info)
-        profs.append(prof)
         log(f"step {k}: {info['status_name']} iters={info['iters']} r={info['r']} "
-            f"passes={info['passes']} wall={dt:.3f}s obj={info['obj']:.8f} "
-            f"rho=({info['rho_p']:.2e},{info['rho_d']:.2e}) rank path {s.rank_path()}")
+            f"passes={info['passes']} verify={info['verify_steps']} wall={dt:.3f}s "
+            f"obj={info['obj']:.8f} rho=({info['rho_p']:.2e},{info['rho_d']:.2e}) "
+            f"rank path {s.rank_path()}")
     ms_per_step = 1000.0 * sum(times) / len(times)
     last = infos[-1]
+    # one more solve with HIP events around every dense pass and dense write
+    # (on the library's stream) gives the per-kernel times of the roofline
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pinfo, prof = one_solve(profile=True)
+    torch.cuda.synchronize()
+    prof_wall = time.perf_counter() - t0
+    profs.append(prof)
+    log(f"profiled solve: {pinfo['status_name']} iters={pinfo['iters']} wall={prof_wall:.3f}s")
     dbg = s.debug()
     _, lam_f = s.factors()
     rank_x = int(np.sum(lam_f > 1e-8 * max(lam_f.max(), 1e-300))) if lam_f.size else 0
@@ -217,19 +234,44 @@ def main():
                          "avg_launch_us": round(write_s / max(write_cnt, 1) * 1e6, 2),
                          "GBps": round(write_bytes / max(write_s, 1e-12) / 1e9, 1),
                          "TFLOPs": round(write_flops / max(write_s, 1e-12) / 1e12, 2)},
-        "sweep_share_of_solve": round((pass_s + write_s) / max(sum(times), 1e-9), 3),
+        "sweep_share_of_solve": round((pass_s + write_s) / max(prof_wall, 1e-9), 3),
+        "profiled_solve_s": round(prof_wall, 4),
     })
+    # the projection sweep (dense passes + dense writes): algorithmic bytes of
+    # the stored layout, and of the unique entries n(n+1)/2 of the symmetric W
+    # and W+ (what a triangle-only layout would have to move), over the summed
+    # kernel time
+    wb = 8 if args.precision == "fp64" else (4 if args.precision == "fp32" else 2)
+    uniq = (pass_cnt + write_cnt) * prob.n * (prob.n + 1) / 2 * wb
+    sweep_s = pass_s + write_s
+    roofline["sweep"] = {
+        "kernels": "dense pass W B + dense write of W+",
+        "bytes": pass_bytes + write_bytes,
+        "seconds": round(sweep_s, 4),
+        "GBps": round((pass_bytes + write_bytes) / max(sweep_s, 1e-12) / 1e9, 1),
+        "frac_hbm": round((pass_bytes + write_bytes) / max(sweep_s, 1e-12) / 1e9 / PEAK_HBM_GBS, 4),
+        "unique_entry_GBps": round(uniq / max(sweep_s, 1e-12) / 1e9, 1),
+    }
     serving = serving_bench(args, dev) if args.serving else None
     full_cmp = None
     if args.workload != "snl" and n <= 4000 and not args.iters:
         full_cmp = full_projection_cost(s, dev, sum(times) / len(times), last)
+    answers = {}
+    if not args.iters:
+        answers[args.precision] = s.solution(on_device=False)
     prec = None
     if not args.no_precision_form and not args.iters and args.precision == "fp64":
-        prec = {name: precision_form(prob, dev, opts, sum(times) / len(times), last, code)
-                for name, code in (("fp32", 1), ("bf16", 2))}
+        prec = {}
+        for name, code in (("fp32", 1), ("bf16", 2)):
+            prec[name], answers[name] = precision_form(prob, dev, opts, sum(times) / len(times),
+                                                       last, code)
     cpu = None
+    check_block = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, last["iters"], args.cpu_iters)
+        if answers and args.workload != "snl":
+            check_block = oracle_check(prob, args.workload, answers,
+                                       {args.precision: last, **(prec or {})})
     out = {
         "metric": "time-to-1e-4 residual (s)" if not args.iters else f"time for {args.iters} iterations (s)",
         "value": round(sum(times) / len(times), 4),
@@ -256,6 +298,7 @@ def main():
         },
         "roofline": roofline,
         "precision_form": prec,
+        "oracle_check": check_block,
         "full_eig_comparison": full_cmp,
         "serving": serving,
         "cpu_baseline": cpu,
@@ -375,7 +418,35 @@ def precision_form(prob, dev, opts, t64, info64, code):
         "lowp_write_avg_us": round(tot[4] / max(tot[5], 1) * 1e3, 2),
         "lowp_write_launches": int(tot[5]),
     }
+    ans = s.solution(on_device=False)
     s.close()
+    return out, ans
+
+
+def oracle_check(prob, workload, answers, infos):
+    """The oracle's certificate of each GPU answer (one exact FP64 PDHG step
+    from it, feasibility, duality gap) and, for max-cut, the certified bracket
+    lower <= p* <= upper (weak duality at a dual-feasible shift of y; a
+    rescaled feasible X), which bounds |obj - p*| without an oracle solve."""
+    import oracle as O
+    out = {}
+    for name, (X, y) in answers.items():
+        t0 = time.perf_counter()
+        c = O.certificate(prob, X, y)
+        obj = infos[name]["obj"]
+        rec = {"cert_rho_p": c.rho_p, "cert_rho_d": c.rho_d, "cert_rho": max(c.rho_p, c.rho_d),
+               "primal_infeas": c.primal_infeas, "dual_infeas": c.dual_infeas,
+               "lambda_min_X": c.lambda_min_X, "rel_gap": c.rel_gap, "obj": obj}
+        if workload == "maxcut":
+            lo, up = O.maxcut_bracket(prob, X, y)
+            rec.update({"bracket_lower": lo, "bracket_upper": up,
+                        "bracket_rel_width": (up - lo) / abs(obj),
+                        "obj_err_bound_rel": max(abs(obj - lo), abs(obj - up)) / abs(obj)})
+        rec["seconds"] = round(time.perf_counter() - t0, 1)
+        log(f"oracle check {name}: cert {rec['cert_rho']:.3e} gap {c.rel_gap:.2e}"
+            + (f" bracket [{rec['bracket_lower']:.6f}, {rec['bracket_upper']:.6f}]"
+               if workload == "maxcut" else "") + f" ({rec['seconds']} s)")
+        out[name] = rec
     return out
 
 

@@ -63,6 +63,24 @@ extern "C" {
 #define PROXSDP_STATUS_MAX_ITERS 2
 #define PROXSDP_STATUS_TIME_LIMIT 3
 #define PROXSDP_STATUS_NUMERICAL 4     /* NaN/Inf in the iterate             */
+/* The residual test passed but Algorithm 2's rank test could not be decided:
+ * after the confirmation rounds of the partial eigensolve the Ritz value
+ * tested lies below the rank-test threshold while its upper estimate (Ritz
+ * value plus the norm of its Ritz residual) lies above it, and r is at its
+ * cap, so the r <- 2r step that the undecided test calls for cannot be taken.
+ * The iterate is returned as it is; it is not certified optimal. */
+#define PROXSDP_STATUS_EIG_NOT_CONVERGED 5
+/* The residual test passed, the rank test failed and r is at its cap
+ * (r_max < n, or the automatic cap of the partial path), so Algorithm 2's
+ * r <- 2r cannot be taken.  The iterate is Algorithm 2's intermediate
+ * feasible solution X_[r] (Section 3.2), not an optimum of the SDP. */
+#define PROXSDP_STATUS_RANK_LIMIT 6
+
+/* Quantity in Algorithm 2's rank test (n - r) max(lambda, 0) <= eps_lambda */
+#define PROXSDP_RANK_TEST_LAMBDA_R 0        /* lambda_r, as Algorithm 2 states it  */
+#define PROXSDP_RANK_TEST_LAMBDA_R_PLUS_1 1 /* lambda_{r+1}, the first excluded
+                                               eigenvalue, which the Section 3.1
+                                               error bound of aproj is about      */
 
 /* storage / arithmetic of the dense n x n iterate and its block products */
 #define PROXSDP_FP64 0
@@ -101,7 +119,10 @@ typedef struct {
                            must be a multiple of check_every                     */
   int32_t check_every;  /* iterations between host-side control checks (10)     */
   int32_t r0;           /* initial target rank (default 1, Algorithm 2)          */
-  int32_t r_max;        /* largest target rank (0 = automatic)                   */
+  int32_t r_max;        /* largest target rank (0 = automatic: n on the exact path,
+                           otherwise 64 with the lambda_r test and 48 with the
+                           lambda_{r+1} test, which needs one more Ritz value
+                           than r inside the 64-wide subspace)                   */
   int32_t full_eig;     /* 1 = PD-SDP (Algorithm 1, exact projection; n <= 64)   */
   int32_t precision;    /* storage of the dense iterate W: PROXSDP_FP64 (default,
                            plain form), PROXSDP_FP32 or PROXSDP_BF16 (precision
@@ -114,7 +135,9 @@ typedef struct {
   int32_t max_iters;    /* default 200000                                        */
   double time_limit_s;  /* default 1200 (the paper's cap); <= 0 = none           */
   int32_t row_scaling;  /* 1 (default): rows scaled to unit Frobenius norm        */
-  int32_t block;        /* subspace width k (0 = automatic, multiple of 16)       */
+  int32_t block;        /* subspace width k (0 = automatic, multiple of 16, <= 64);
+                           a fixed width also caps r at k (k - 1 with the
+                           lambda_{r+1} rank test)                               */
   double eig_tol;       /* relative Ritz residual target of the partial
                            eigensolve, floor of the adaptive schedule (1e-10)    */
   int32_t max_passes;   /* max dense passes per iteration (default 8)             */
@@ -131,6 +154,11 @@ typedef struct {
                            graphs and replayed (fewer launches; serving); needs
                            a stream other than the null stream.  0 (default):
                            every kernel is launched directly                    */
+  int32_t rank_test;    /* PROXSDP_RANK_TEST_LAMBDA_R (default, Algorithm 2) or
+                           PROXSDP_RANK_TEST_LAMBDA_R_PLUS_1.  On the partial
+                           path a passing test is confirmed on a converged
+                           subspace and must hold for the upper estimate
+                           theta + ||W u - theta u|| of the tested Ritz pair   */
 } proxsdp_options;
 
 /* ------------------------------------------------------------- info */
@@ -151,6 +179,20 @@ typedef struct {
   double norm_M;        /* ||M||_2 of the (scaled) operator                        */
   double ritz_res;      /* largest relative Ritz residual of the kept pairs        */
   double time_s;        /* wall time inside step/solve since create                */
+  double gap;           /* |obj - dual_obj| / (1 + |obj| + |dual_obj|) at the last check */
+  double rank_value;    /* value of the last rank test decided on a confirmed
+                           subspace: upper estimate of lambda_r (or lambda_{r+1}),
+                           NaN if none was taken                                  */
+  int32_t saved;        /* number of intermediate solutions X_[r] kept so far      */
+  int32_t verify_steps; /* exact-step convergence checks taken: once the residual
+                           and rank tests pass on the partial path with the
+                           adaptive eigensolve accuracy, one more iteration runs
+                           with every kept Ritz pair converged to eig_tol, and
+                           the solve stops only if that exact step's residuals
+                           meet tol; otherwise the iteration continues, with
+                           eig_rel scaled by 0.1 / (q - 1) (floor 1e-3) when the
+                           exact step's residual is q > 1.1 times the reported
+                           one                                                   */
 } proxsdp_info;
 
 typedef struct proxsdp_handle proxsdp_handle;
@@ -218,6 +260,20 @@ int proxsdp_get_factors(proxsdp_handle *h, double *V, double *lambda, int32_t *r
  * take it out for a later warm start. */
 int proxsdp_get_state(proxsdp_handle *h, double *V, double *lambda, double *y, int32_t *r_out);
 
+/* Intermediate feasible solutions X_[r] of Algorithm 2 (Section 3.2): every
+ * time the residual test passes and the rank test fails, before r doubles (or
+ * before the solve stops with PROXSDP_STATUS_RANK_LIMIT /
+ * EIG_NOT_CONVERGED), the handle keeps a host copy of that iterate: its
+ * factors X_[r] = V diag(lambda) V^T (V n x r row-major, lambda r values) and
+ * its dual y_[r] (m + p values, unscaled, Section 1.3 sign).  `idx` counts
+ * from 0 in the order they were kept; *iter_out gets the iteration after which
+ * the copy was made and *r_out its rank.  Any output pointer may be NULL (a
+ * call with NULL arrays returns r).  proxsdp_saved_count gives how many exist.
+ * reset / set_state drop them.  Errors: PROXSDP_ERR_INVALID for a bad idx. */
+int proxsdp_saved_count(proxsdp_handle *h, int32_t *count);
+int proxsdp_get_saved(proxsdp_handle *h, int32_t idx, double *V, double *lambda, double *y,
+                      int32_t *r_out, int32_t *iter_out);
+
 /* Warm start: restarts the iteration (counters, rank control and history
  * cleared, as proxsdp_reset) from X0 = V diag(lambda) V^T and y0 instead of
  * X0 = 0, y0 = 0 (Algorithm 1 from a given point).  V: n x r row-major host
@@ -258,7 +314,8 @@ int proxsdp_profile_totals(proxsdp_handle *h, double *out, int32_t count);
 /* Rank path of Algorithm 2 since create/reset: for each change of the target
  * rank, the iteration after which it happened, the new rank and the reason
  * (1 = residual converged but the rank test failed, 2 = the windowed residual
- * test found no decrease).  Writes up to `cap` entries; *count gets the total.
+ * test found no decrease, 3 = residual converged and the rank test could not
+ * be decided on a confirmed subspace).  Writes up to `cap` entries; *count gets the total.
  * Host pointers; any may be NULL. */
 int proxsdp_rank_path(proxsdp_handle *h, int32_t *iters, int32_t *ranks, int32_t *reasons,
                       int32_t cap, int32_t *count);

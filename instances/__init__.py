@@ -44,6 +44,7 @@ __all__ = [
     "complete_edges",
     "from_edges_maxcut",
     "from_edges_equipartition",
+    "planted_lowrank",
 ]
 
 
@@ -179,6 +180,28 @@ def equipartition(n: int, p_edge: float, seed: int) -> Problem:
     return from_edges_equipartition(n, erdos_renyi_edges(n, p_edge, seed),
                                     name=f"equip_n{n}_p{p_edge}_s{seed}",
                                     meta=dict(kind="equipartition", p_edge=p_edge, seed=seed))
+
+
+def planted_lowrank(n: int, rank: int, seed: int) -> Problem:
+    """Diagonal-constrained SDP with a dense rank-``rank`` cost (a test case
+    with a planted spectral gap): minimize <C, X> s.t. X_ii = 1, X PSD, with
+    C = -U diag(s) U^T, U an n x rank Haar-orthonormal block (QR of a PCG64
+    Gaussian matrix seeded with ``seed``) and s spaced evenly from 2 n / rank
+    down to n / rank.  The first iterates W = -alpha C have exactly ``rank``
+    positive eigenvalues and a zero bulk, so a partial eigensolve of width
+    k >= rank converges in a few rounds.  C is passed as its full upper
+    triangle (n (n + 1) / 2 triplets).
+    """
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((n, rank)))
+    s = np.linspace(2.0, 1.0, rank) * (n / rank)
+    C = -(U * s) @ U.T
+    iu, ju = np.triu_indices(n)
+    a_row, a_i, a_j, a_v = _diag_rows(n)
+    return Problem(n=n, m=n, p=0, c_i=iu, c_j=ju, c_v=C[iu, ju],
+                   a_row=a_row, a_i=a_i, a_j=a_j, a_v=a_v, b=np.ones(n), h=np.zeros(0),
+                   name=f"planted_n{n}_r{rank}_s{seed}",
+                   meta=dict(kind="planted_lowrank", rank=rank, seed=seed))
 
 
 # ------------------------------------------------------------------------ SNL

@@ -23,7 +23,13 @@ STATUS_CONVERGED = 1
 STATUS_MAX_ITERS = 2
 STATUS_TIME_LIMIT = 3
 STATUS_NUMERICAL = 4
-STATUS_NAMES = {0: "running", 1: "converged", 2: "max_iters", 3: "time_limit", 4: "numerical"}
+STATUS_EIG_NOT_CONVERGED = 5
+STATUS_RANK_LIMIT = 6
+STATUS_NAMES = {0: "running", 1: "converged", 2: "max_iters", 3: "time_limit", 4: "numerical",
+                5: "eig_not_converged", 6: "rank_limit"}
+
+RANK_TEST_LAMBDA_R = 0
+RANK_TEST_LAMBDA_R_PLUS_1 = 1
 
 FP64, FP32, BF16 = 0, 1, 2
 
@@ -49,6 +55,7 @@ class Options(C.Structure):
         ("max_iters", C.c_int32), ("time_limit_s", C.c_double), ("row_scaling", C.c_int32),
         ("block", C.c_int32), ("eig_tol", C.c_double), ("max_passes", C.c_int32),
         ("seed", C.c_int32), ("eig_strict", C.c_int32), ("eig_rel", C.c_double), ("graphs", C.c_int32),
+        ("rank_test", C.c_int32),
     ]
 
 
@@ -60,7 +67,8 @@ class Info(C.Structure):
         ("eps_p", C.c_double), ("eps_d", C.c_double), ("rho_p", C.c_double),
         ("rho_d", C.c_double), ("obj", C.c_double), ("dual_obj", C.c_double),
         ("alpha", C.c_double), ("norm_M", C.c_double), ("ritz_res", C.c_double),
-        ("time_s", C.c_double),
+        ("time_s", C.c_double), ("gap", C.c_double), ("rank_value", C.c_double),
+        ("saved", C.c_int32), ("verify_steps", C.c_int32),
     ]
 
     def to_dict(self) -> dict:
@@ -92,6 +100,8 @@ def _load():
         "proxsdp_get_factors": (C.c_int, [H, _f64p, _f64p, _i32p]),
         "proxsdp_get_state": (C.c_int, [H, _f64p, _f64p, _f64p, _i32p]),
         "proxsdp_set_state": (C.c_int, [H, C.c_int32, _f64p, _f64p, _f64p]),
+        "proxsdp_saved_count": (C.c_int, [H, _i32p]),
+        "proxsdp_get_saved": (C.c_int, [H, C.c_int32, _f64p, _f64p, _f64p, _i32p, _i32p]),
         "proxsdp_destroy": (None, [H]),
         "proxsdp_project_workspace_size": (C.c_int, [C.c_int32, C.c_int32, C.c_int32,
                                                      C.POINTER(C.c_size_t)]),

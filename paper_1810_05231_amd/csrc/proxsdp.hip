@@ -124,8 +124,10 @@ int validate(const proxsdp_problem* pb, const proxsdp_options* o) {
     if (o->full_eig && pb->n > KMAX)
       return fail(PROXSDP_ERR_UNSUPPORTED, "full_eig needs n <= " + std::to_string(KMAX));
     if (!(o->eig_rel > 0)) return fail(PROXSDP_ERR_INVALID, "eig_rel must be > 0");
-    if (o->block && (o->block % 16 || o->block > KMAX))
+    if (o->block && (o->block < 0 || o->block % 16 || o->block > KMAX))
       return fail(PROXSDP_ERR_INVALID, "block must be a multiple of 16 and <= 64");
+    if (o->rank_test != PROXSDP_RANK_TEST_LAMBDA_R && o->rank_test != PROXSDP_RANK_TEST_LAMBDA_R_PLUS_1)
+      return fail(PROXSDP_ERR_INVALID, "rank_test must be PROXSDP_RANK_TEST_LAMBDA_R or _PLUS_1");
   }
   return PROXSDP_OK;
 }
@@ -476,6 +478,15 @@ struct proxsdp_handle {
   std::vector<double> hist;
   std::vector<int> path_it, path_r, path_why;
   double eps_lambda = 0;
+  double rank_value = std::nan("");   // last confirmed rank-test value (upper estimate)
+  int verify_steps = 0;               // exact-step convergence checks taken
+  double eig_rel_user = 0.2;          // eig_rel as created (the checks may lower it)
+  // Algorithm 2's intermediate feasible solutions X_[r] (host copies)
+  struct Saved {
+    int iter = 0, r = 0;
+    std::vector<double> V, lam, y;
+  };
+  std::vector<Saved> saved;
   double time_s = 0;
   proxsdp_info last{};
   size_t ws_need = 0;
@@ -591,8 +602,13 @@ static void setup_dims(proxsdp_handle* H) {
     H->r_cap = h.n;
     H->k_cap = 16;
   } else {
-    const int rmax_auto = 48;
+    // Algorithm 2 doubles r up to n; the partial path holds at most KMAX Ritz
+    // pairs, so r stops at KMAX (KMAX - 16 with the lambda_{r+1} test, which
+    // needs a Ritz value beyond r).  A fixed subspace width caps r at k (k - 1).
+    const bool plus1 = H->opt.rank_test == PROXSDP_RANK_TEST_LAMBDA_R_PLUS_1;
+    const int rmax_auto = plus1 ? KMAX - 16 : KMAX;
     H->r_cap = std::min(h.n, H->opt.r_max > 0 ? std::min(H->opt.r_max, rmax_auto) : rmax_auto);
+    if (H->opt.block) H->r_cap = std::min(H->r_cap, H->opt.block - (plus1 ? 1 : 0));
     H->k_cap = H->opt.block ? H->opt.block : k_for_r(H->r_cap);
     H->k_cap = std::max(H->k_cap, 16);
   }
@@ -1108,41 +1124,112 @@ static int fill_info(proxsdp_handle* H, const IterRecord& rec, double nonfinite)
   I.norm_M = H->h.norm_m;
   I.ritz_res = rec.maxres;
   I.time_s = H->time_s;
+  I.gap = std::fabs(rec.obj - rec.dual_obj) / (1.0 + std::fabs(rec.obj) + std::fabs(rec.dual_obj));
+  I.rank_value = H->rank_value;
+  I.saved = (int32_t)H->saved.size();
+  I.verify_steps = H->verify_steps;
   (void)nonfinite;
   return PROXSDP_OK;
 }
 
-// lambda_r of the current W for the rank test, from a converged subspace:
-// eight filtered eigensolver rounds (dense pass or exact apply, Rayleigh-Ritz,
-// next basis), the last one on the Cholesky path (every Ritz value resolved;
-// the Newton path leaves the non-positive tail unresolved).  A single round
-// on the iteration's basis can underestimate lambda_r (Ritz values interlace
-// from below) when a dense cluster of small eigenvalues has not converged.
-// Overwrites only data the next iteration recomputes (and improves the basis).
-static int confirm_lambda_r(proxsdp_handle* H, double* lam_r) {
+// Rank test of Algorithm 2 on a confirmed subspace.  Rounds of the partial
+// eigensolve (dense pass or exact apply, Rayleigh-Ritz on the Cholesky path,
+// which resolves every Ritz value, next basis) on the current W, in batches of
+// eight; after each batch the true Ritz residuals ||W u_c - theta_c u_c|| of
+// the columns up to r + 1 are formed from the same pass.  A Ritz value is a
+// lower bound of the eigenvalue of the same index (interlacing), and the
+// residual norm bounds the distance to an eigenvalue, so the test is decided
+// on the pair (theta, theta + ||res||) of the tested index: it fails when even
+// theta is above the threshold, passes when theta + ||res|| is below it, and
+// another batch runs while it is undecided (at most four).  Overwrites only
+// data the next iteration recomputes (and improves the basis).
+enum RankVerdict { RANK_PASS = 0, RANK_FAIL = 1, RANK_UNDECIDED = 2 };
+
+static int rank_probe(proxsdp_handle* H, double thr, int* verdict, double* ub_out) {
   hipStream_t st = H->st;
   const int slot = H->iters & 1;   // lambda slot the next iteration overwrites
-  const int rounds = 8;
-  for (int rd = 0; rd < rounds; ++rd) {
-    const double* Bc = H->B[H->bcur];
-    if (H->prec == PROXSDP_FP64) {
-      launch_block(H->W, H->npad, H->n, H->npad, Bc, H->k, H->part, H->ch, true, st);
-      launch_reduce(H->part, H->ch.nchunks, H->Z, Bc, nullptr, H->npad, H->k, H->gram_part, 0, 0.0,
-                    1.0, true, st);
-    } else {
-      launch_implicit(H, Bc, H->Z);
-    }
-    launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(slot), 1, 1e-15, st,
-              rd == rounds - 1 ? 0 : 10);
-    if (rd < rounds - 1) {
-      const int nb = (H->bcur + 1) % 3;
-      launch_rowwise(H, Bc, nullptr, H->r, nullptr, 0, H->B[nb], st);
-      H->bcur = nb;
-    }
-    H->passes += 1;
+  const bool plus1 = H->opt.rank_test == PROXSDP_RANK_TEST_LAMBDA_R_PLUS_1;
+  const int idx = plus1 ? H->r : H->r - 1;   // 0-based index of the tested value
+  if (idx >= H->k) {
+    // no such Ritz value in the subspace (the caps keep r + 1 <= k for this test)
+    *verdict = RANK_UNDECIDED;
+    *ub_out = std::nan("");
+    return PROXSDP_OK;
   }
-  HIP_OK(hipMemcpyAsync(lam_r, H->small + SL::SC + S_LAMR, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_OK(hipStreamSynchronize(st));
+  const int ncol = idx + 1;
+  const int per_batch = 8, batches = 4;
+  *verdict = RANK_UNDECIDED;
+  for (int b = 0; b < batches && *verdict == RANK_UNDECIDED; ++b) {
+    for (int rd = 0; rd < per_batch; ++rd) {
+      const bool last = rd == per_batch - 1;
+      const double* Bc = H->B[H->bcur];
+      if (H->prec == PROXSDP_FP64) {
+        launch_block(H->W, H->npad, H->n, H->npad, Bc, H->k, H->part, H->ch, true, st);
+        launch_reduce(H->part, H->ch.nchunks, H->Z, Bc, nullptr, H->npad, H->k, H->gram_part, 0,
+                      0.0, 1.0, true, st);
+      } else {
+        launch_implicit(H, Bc, H->Z);
+      }
+      launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(slot), 1, 1e-15, st,
+                last ? 0 : 10);
+      const int nb = (H->bcur + 1) % 3;
+      // the last round of a batch also forms the true residuals of columns < ncol
+      launch_rowwise(H, Bc, nullptr, last ? ncol : H->r, nullptr, 0, H->B[nb], st);
+      H->bcur = nb;
+      H->passes += 1;
+    }
+    hipLaunchKernelGGL(k_reduce_res, dim3(1), dim3(256), 0, st, H->fac_part, H->nsl, ncol, H->small);
+    double th = 0, rel = 0, scale = 0;
+    HIP_OK(hipMemcpyAsync(&th, H->small + SL::THETA + idx, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&rel, H->small + SL::RES + idx, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&scale, H->small + SL::SC + S_NORMW, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    const double ub = th + rel * std::max(scale, 1e-300);
+    *ub_out = ub;
+    if (!std::isfinite(ub)) break;
+    if (std::max(th, 0.0) > thr) *verdict = RANK_FAIL;
+    else if (std::max(ub, 0.0) <= thr) *verdict = RANK_PASS;
+  }
+  return PROXSDP_OK;
+}
+
+// One PDHG iteration whose partial eigensolve runs until the kept Ritz pairs
+// meet eig_tol (the eig_strict schedule), i.e. the exact step of Algorithm 1
+// from the current (X, y) once the rank test has shown that r covers every
+// positive eigenvalue.  Its residuals are those of an exact step, which is
+// what decides convergence (Section 2.2: the fixed point of the exact
+// iteration is the KKT point); the adaptive-accuracy iterations before it
+// only report residuals of their own inexact steps.  *out gets its record.
+static int verify_step(proxsdp_handle* H, IterRecord* out) {
+  const int strict = H->opt.eig_strict;
+  H->opt.eig_strict = 1;
+  iterate_once(H);
+  H->opt.eig_strict = strict;
+  std::vector<IterRecord> recs;
+  int rc = read_records(H, H->iters - 1, 1, recs);
+  if (rc) return rc;
+  HIP_OK(hipStreamSynchronize(H->st));
+  *out = recs[0];
+  H->verify_steps += 1;
+  return PROXSDP_OK;
+}
+
+// Host copy of the current iterate as Algorithm 2's intermediate X_[r].
+static int save_intermediate(proxsdp_handle* H) {
+  proxsdp_handle::Saved sv;
+  sv.iter = H->iters;
+  int32_t r = 0;
+  int rc = proxsdp_get_factors(H, nullptr, nullptr, &r);
+  if (rc) return rc;
+  sv.r = r;
+  sv.V.assign((size_t)H->n * std::max(r, 1), 0.0);
+  sv.lam.assign(std::max(r, 1), 0.0);
+  sv.y.assign(H->rows, 0.0);
+  rc = proxsdp_get_factors(H, sv.V.data(), sv.lam.data(), &r);
+  if (rc) return rc;
+  rc = proxsdp_get_solution(H, nullptr, sv.y.data(), 0);
+  if (rc) return rc;
+  H->saved.push_back(std::move(sv));
   return PROXSDP_OK;
 }
 
@@ -1182,21 +1269,59 @@ static int control(proxsdp_handle* H) {
   if (nonfinite != 0.0 || !std::isfinite(comb)) {
     H->status = PROXSDP_STATUS_NUMERICAL;
   } else if (std::max(rho_p, rho_d) <= H->opt.tol) {
+    // Algorithm 2: converged residuals stop the solve only if the rank test
+    // (n - r) max(lambda, 0) <= eps_lambda passes; otherwise X_[r] is kept and
+    // r doubles (at the cap the solve stops with a status saying so).
     const int n = H->n;
-    bool pass = H->r >= n || (double)(n - H->r) * std::max(rec.lambda_r, 0.0) <= H->eps_lambda;
-    if (pass && H->r < n && !H->full) {
-      double lr = rec.lambda_r;
-      const int rc = confirm_lambda_r(H, &lr);
-      if (rc) return rc;
-      pass = (double)(n - H->r) * std::max(lr, 0.0) <= H->eps_lambda;
+    const bool plus1 = H->opt.rank_test == PROXSDP_RANK_TEST_LAMBDA_R_PLUS_1;
+    int verdict = RANK_PASS;
+    if (H->r < n) {
+      const double thr = H->eps_lambda / (double)(n - H->r);
+      if (H->full) {
+        const double lam_t = plus1 ? rec.lambda_r1 : rec.lambda_r;   // exact eigenvalues
+        verdict = std::max(lam_t, 0.0) <= thr ? RANK_PASS : RANK_FAIL;
+      } else if (!plus1 && std::max(rec.lambda_r, 0.0) > thr) {
+        // a positive r-th Ritz value is kept, hence resolved, and bounds
+        // lambda_r from below: the test fails without confirmation
+        verdict = RANK_FAIL;
+      } else {
+        double ub = 0;
+        const int rc2 = rank_probe(H, thr, &verdict, &ub);
+        if (rc2) return rc2;
+        H->rank_value = ub;
+      }
     }
-    if (pass) {
+    if (verdict == RANK_PASS && !H->full && !H->opt.eig_strict) {
+      // the residuals above are those of an inexact step: decide on an exact one
+      IterRecord vr{};
+      const int rc4 = verify_step(H, &vr);
+      if (rc4) return rc4;
+      const double vp = vr.eps_p / (1.0 + H->h.norm_c), vd = vr.eps_d / (1.0 + H->h.norm_rhs);
+      if (std::max(vp, vd) <= H->opt.tol && std::isfinite(vp + vd)) {
+        H->status = PROXSDP_STATUS_CONVERGED;
+        fill_info(H, vr, nonfinite);
+        return PROXSDP_OK;
+      }
+      // The exact step's residual q times the inexact one's: the excess q - 1
+      // is the bias of the reported residuals, which scales with the eigen
+      // error allowed per step (eig_rel).  Bring it down to about 0.1 (no
+      // change for a residual that only sat on the threshold); iterate on.
+      const double q = std::max(vp, vd) / std::max(std::max(rho_p, rho_d), 1e-300);
+      if (q > 1.1)
+        H->opt.eig_rel = std::max(H->opt.eig_rel * std::min(1.0, 0.1 / (q - 1.0)), 1e-3);
+      H->hist.push_back(vr.eps_p + vr.eps_d);
+    } else if (verdict == RANK_PASS) {
       H->status = PROXSDP_STATUS_CONVERGED;
-    } else if (H->r >= H->r_cap) {
-      H->hist.push_back(comb);
     } else {
-      set_rank(H, std::min(2 * H->r, H->r_cap), 1);
-      H->hist.clear();
+      const int rc3 = save_intermediate(H);
+      if (rc3) return rc3;
+      if (H->r >= H->r_cap) {
+        H->status = verdict == RANK_FAIL ? PROXSDP_STATUS_RANK_LIMIT
+                                         : PROXSDP_STATUS_EIG_NOT_CONVERGED;
+      } else {
+        set_rank(H, std::min(2 * H->r, H->r_cap), verdict == RANK_FAIL ? 1 : 3);
+        H->hist.clear();
+      }
     }
   } else {
     H->hist.push_back(comb);
@@ -1286,6 +1411,10 @@ static int reset_buffers(proxsdp_handle* H) {
   H->path_it.clear();
   H->path_r.clear();
   H->path_why.clear();
+  H->saved.clear();
+  H->rank_value = std::nan("");
+  H->verify_steps = 0;
+  H->opt.eig_rel = H->eig_rel_user;
   H->time_s = 0;
   H->last = proxsdp_info{};
   H->bcur = 0;
@@ -1337,6 +1466,7 @@ int proxsdp_default_options(proxsdp_options* o) {
   o->seed = 1;
   o->eig_strict = 0;
   o->eig_rel = 0.2;
+  o->rank_test = PROXSDP_RANK_TEST_LAMBDA_R;
   return PROXSDP_OK;
 }
 
@@ -1384,6 +1514,7 @@ int proxsdp_create(const proxsdp_problem* pb, const proxsdp_options* opt, void* 
   const Host& h = H->h;
   H->opt.alpha = (o.alpha > 0) ? o.alpha : 0.95 / h.norm_m;
   H->eps_lambda = (o.eps_lambda >= 0) ? o.eps_lambda : o.tol;
+  H->eig_rel_user = o.eig_rel;
   hipStream_t st = H->st;
   const DevProblem& d = H->dp;
 #define UP(dst, src) if ((rc = up(dst, src, st))) { delete H; return rc; }
@@ -1662,6 +1793,28 @@ int proxsdp_set_state(proxsdp_handle* H, int32_t r, const double* V, const doubl
   return PROXSDP_OK;
 }
 
+int proxsdp_saved_count(proxsdp_handle* H, int32_t* count) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  if (count) *count = (int32_t)H->saved.size();
+  return PROXSDP_OK;
+}
+
+int proxsdp_get_saved(proxsdp_handle* H, int32_t idx, double* V, double* lambda, double* y,
+                      int32_t* r_out, int32_t* iter_out) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  if (idx < 0 || idx >= (int)H->saved.size())
+    return fail(PROXSDP_ERR_INVALID, "saved index out of range");
+  const proxsdp_handle::Saved& sv = H->saved[idx];
+  if (r_out) *r_out = sv.r;
+  if (iter_out) *iter_out = sv.iter;
+  if (V && sv.r > 0) std::memcpy(V, sv.V.data(), (size_t)H->n * sv.r * sizeof(double));
+  if (lambda && sv.r > 0) std::memcpy(lambda, sv.lam.data(), (size_t)sv.r * sizeof(double));
+  if (y) std::memcpy(y, sv.y.data(), (size_t)H->rows * sizeof(double));
+  return PROXSDP_OK;
+}
+
 int proxsdp_get_state(proxsdp_handle* H, double* V, double* lambda, double* y, int32_t* r_out) {
   g_err.clear();
   if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
@@ -1892,36 +2045,22 @@ int proxsdp_project_workspace_size(int32_t n, int32_t r, int32_t precision, size
   return PROXSDP_OK;
 }
 
-int proxsdp_project_psd(const void* S, int32_t n, int64_t lds, int32_t r, int32_t precision,
-                        double tol, void* P, int64_t ldp, double* evals, double* evecs,
-                        int32_t* rank_out, void* ws, size_t ws_bytes, void* stream) {
-  g_err.clear();
-  if (!S) return fail(PROXSDP_ERR_INVALID, "S is NULL");
-  if (n < 1 || lds < n) return fail(PROXSDP_ERR_INVALID, "need n >= 1 and lds >= n");
-  if (P && ldp < n) return fail(PROXSDP_ERR_INVALID, "ldp < n");
-  size_t need = 0;
-  int rc = proxsdp_project_workspace_size(n, r, precision, &need);
-  if (rc) return rc;
-  if (!ws) return fail(PROXSDP_ERR_WORKSPACE, "workspace is NULL");
-  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PROXSDP_ERR_WORKSPACE, "workspace not 256-byte aligned");
-  if (ws_bytes < need) return fail(PROXSDP_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
-  if ((rc = set_lds_limits())) return rc;
-  if (!(tol > 0)) tol = 1e-12;
-  const int re = (r == 0 || r >= n) ? n : r;
-  if (n > KMAX && re == n)
-    return project_full_large(static_cast<const double*>(S), n, lds, tol, static_cast<double*>(P), ldp,
-                              evals, evecs, rank_out, ws, ws_bytes, static_cast<hipStream_t>(stream));
+// aproj / proj of a device matrix for the paths that need no library routine
+// (one-workgroup Jacobi for n <= KMAX, partial eigensolve otherwise), with the
+// device memory at `ws` (project_layout bytes, 256-byte aligned).
+static int project_core(const double* Sd, int n, int64_t lds, int re, double tol, double* P,
+                        int64_t ldp, double* evals, double* evecs, int32_t* rank_out, void* ws,
+                        hipStream_t st) {
+  int rc = 0;
   proxsdp_handle H;
-  H.st = static_cast<hipStream_t>(stream);
+  H.st = st;
   double* gpart = nullptr;
   project_layout(&H, n, re, ws, &gpart);
   H.dp.n = n;
   H.dp.npad = H.npad;
   H.dp.tiles_side = H.npad / TILE;
-  hipStream_t st = H.st;
   zero(H.small, SL::TOTAL, st);
   zero(H.V[0], (size_t)H.npad * KMAX, st);
-  const double* Sd = static_cast<const double*>(S);
   const int lam_off = lam_slot(0);
   if (H.full) {
     const size_t lds_b = (2 * (size_t)n * (n + 1) + n + 3 * (KMAX / 2 + 1)) * sizeof(double) + (KMAX + 4) * sizeof(int);
@@ -1979,6 +2118,29 @@ int proxsdp_project_psd(const void* S, int32_t n, int64_t lds, int32_t r, int32_
     *rank_out = c;
   }
   return PROXSDP_OK;
+}
+
+int proxsdp_project_psd(const void* S, int32_t n, int64_t lds, int32_t r, int32_t precision,
+                        double tol, void* P, int64_t ldp, double* evals, double* evecs,
+                        int32_t* rank_out, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!S) return fail(PROXSDP_ERR_INVALID, "S is NULL");
+  if (n < 1 || lds < n) return fail(PROXSDP_ERR_INVALID, "need n >= 1 and lds >= n");
+  if (P && ldp < n) return fail(PROXSDP_ERR_INVALID, "ldp < n");
+  size_t need = 0;
+  int rc = proxsdp_project_workspace_size(n, r, precision, &need);
+  if (rc) return rc;
+  if (!ws) return fail(PROXSDP_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PROXSDP_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < need) return fail(PROXSDP_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  if ((rc = set_lds_limits())) return rc;
+  if (!(tol > 0)) tol = 1e-12;
+  const int re = (r == 0 || r >= n) ? n : r;
+  if (n > KMAX && re == n)
+    return project_full_large(static_cast<const double*>(S), n, lds, tol, static_cast<double*>(P), ldp,
+                              evals, evecs, rank_out, ws, ws_bytes, static_cast<hipStream_t>(stream));
+  return project_core(static_cast<const double*>(S), n, lds, re, tol, static_cast<double*>(P), ldp,
+                      evals, evecs, rank_out, ws, static_cast<hipStream_t>(stream));
 }
 
 int proxsdp_reset(proxsdp_handle* H) {

@@ -199,11 +199,37 @@ class Solver:
         d["theta"] = out[64:].tolist()
         return d
 
+    def saved(self):
+        """Algorithm 2's intermediate feasible solutions X_[r] kept so far:
+        [(iteration, V, lambda, y)] with X_[r] = V diag(lambda) V^T, y unscaled."""
+        cnt = C.c_int32()
+        check(lib.proxsdp_saved_count(self._h, C.byref(cnt)), "saved_count")
+        p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        out = []
+        for i in range(cnt.value):
+            r = C.c_int32()
+            it = C.c_int32()
+            check(lib.proxsdp_get_saved(self._h, i, None, None, None, C.byref(r), C.byref(it)),
+                  "get_saved")
+            V = np.zeros((self.n, max(r.value, 1)))
+            lam = np.zeros(max(r.value, 1))
+            y = np.zeros(self.rows)
+            check(lib.proxsdp_get_saved(self._h, i, p(V), p(lam), p(y), C.byref(r), C.byref(it)),
+                  "get_saved")
+            out.append((int(it.value), V[:, :r.value].copy(), lam[:r.value].copy(), y))
+        return out
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib.proxsdp_destroy(self._h)
             self._h = C.c_void_p()
         self._buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 STEP_UNTIL_ANY_STOPS = 1
@@ -223,12 +249,6 @@ def step_many(solvers, n_iters: int, until_any_stops: bool = False):
                                 STEP_UNTIL_ANY_STOPS if until_any_stops else 0,
                                 C.cast(infos, C.c_void_p)), "proxsdp_step_many")
     return [infos[i].to_dict() for i in range(cnt)]
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
 
 def project_psd(S, r: int, tol: float = 1e-12, want_P: bool = True, want_vectors: bool = False):

@@ -121,6 +121,25 @@ def test_rejects_zero_row_and_bad_options():
     _expect_error(L.PROXSDP_ERR_INVALID, p, tol=0.0)
     _expect_error(L.PROXSDP_ERR_UNSUPPORTED, I.maxcut(100, 0.1, 0), full_eig=1)
     _expect_error(L.PROXSDP_ERR_INVALID, p, block=24)
+    _expect_error(L.PROXSDP_ERR_INVALID, p, rank_test=2)
+    _expect_error(L.PROXSDP_ERR_INVALID, p, block=-16)
+
+
+def test_fixed_block_caps_the_rank():
+    # a fixed subspace width k caps r at k (k - 1 with the lambda_{r+1} test):
+    # the workspace of block=16 does not grow with r0 or r_max (the factor
+    # and basis blocks are sized by the width), so r can never exceed k
+    L = _lib()
+    p = I.maxcut(300, 0.05, 0)
+    s16 = _size(p, block=16)
+    assert _size(p, block=16, r0=40, r_max=60) == s16
+    assert _size(p, block=16, rank_test=L.RANK_TEST_LAMBDA_R_PLUS_1) == s16
+    assert _size(p, r0=40) > s16
+
+
+def test_default_rank_test_is_lambda_r():
+    L = _lib()
+    assert L.default_options().rank_test == L.RANK_TEST_LAMBDA_R
 
 
 def test_project_workspace_size_limits():
