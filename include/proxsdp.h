@@ -359,6 +359,22 @@ int proxsdp_project_psd(const void *S, int32_t n, int64_t lds, int32_t r, int32_
                         double tol, void *P, int64_t ldp, double *evals, double *evecs,
                         int32_t *rank_out, void *d_workspace, size_t ws_bytes, void *stream);
 
+/* proxsdp_project_psd for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same computation and arguments, without the workspace.
+ * Its device memory is a static 32 MiB array that the library holds on every
+ * GPU it runs on until the process ends (enough for n = 2000 at r <= 48, or
+ * n up to about 2800 at r = 16); it calls no hipMalloc / hipFree and no
+ * allocating library routine.  Every call on one GPU shares that GPU's array
+ * and overwrites it, so calls that overlap on one GPU (other threads, other
+ * streams) race; serialise them.  The exact projection for n > 64 (r = 0 or
+ * r >= n) needs rocSOLVER and is refused with PROXSDP_ERR_UNSUPPORTED; a size
+ * whose scratch (proxsdp_project_workspace_size) exceeds 32 MiB is refused
+ * with PROXSDP_ERR_WORKSPACE.  Synchronises `stream`. */
+int proxsdp_project_psd_noalloc(const void *S, int32_t n, int64_t lds, int32_t r, int32_t precision,
+                                double tol, void *P, int64_t ldp, double *evals, double *evecs,
+                                int32_t *rank_out, void *stream);
+
 /* Thread-local description of the last error (empty string if none). */
 const char *proxsdp_last_error(void);
 

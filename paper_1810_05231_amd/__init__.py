@@ -4,6 +4,6 @@
 library libproxsdp.so behind the C interface of include/proxsdp.h.
 """
 from ._lib import FP32, FP64, BF16, ProxSDPError, lib  # noqa: F401
-from .solver import Solver, project_psd, workspace_size  # noqa: F401
+from .solver import Solver, project_psd, project_psd_noalloc, workspace_size  # noqa: F401
 
-__all__ = ["Solver", "project_psd", "workspace_size", "ProxSDPError", "lib"]
+__all__ = ["Solver", "project_psd", "project_psd_noalloc", "workspace_size", "ProxSDPError", "lib"]

@@ -109,6 +109,9 @@ def _load():
                                           C.c_int32, C.c_double, C.c_void_p, C.c_int64,
                                           _f64p, _f64p, _i32p, C.c_void_p, C.c_size_t,
                                           C.c_void_p]),
+        "proxsdp_project_psd_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int32,
+                                                  C.c_int32, C.c_double, C.c_void_p, C.c_int64,
+                                                  _f64p, _f64p, _i32p, C.c_void_p]),
         "proxsdp_reset": (C.c_int, [H]),
         "proxsdp_profile_enable": (C.c_int, [H, C.c_int32]),
         "proxsdp_profile_read": (C.c_int, [H, _f64p, _i32p, _f64p, _i32p]),

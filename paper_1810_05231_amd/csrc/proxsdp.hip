@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <tuple>
 #include <string>
@@ -2139,6 +2140,62 @@ int proxsdp_project_psd(const void* S, int32_t n, int64_t lds, int32_t r, int32_
   if (n > KMAX && re == n)
     return project_full_large(static_cast<const double*>(S), n, lds, tol, static_cast<double*>(P), ldp,
                               evals, evecs, rank_out, ws, ws_bytes, static_cast<hipStream_t>(stream));
+  return project_core(static_cast<const double*>(S), n, lds, re, tol, static_cast<double*>(P), ldp,
+                      evals, evecs, rank_out, ws, static_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------ allocation-free projection
+// Device memory of proxsdp_project_psd_noalloc: one file-scope array, which
+// every GPU the library runs on holds (its own copy) until the process ends.
+// Host code must not pass `scratch` itself to a kernel (that is a host-side
+// stand-in, not a device address): its device address is looked up once per
+// device with hipGetSymbolAddress and kept in g_scratch_dev.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+static int scratch_address(void** out) {
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(PROXSDP_ERR_UNSUPPORTED, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PROXSDP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return PROXSDP_OK;
+}
+
+int proxsdp_project_psd_noalloc(const void* S, int32_t n, int64_t lds, int32_t r, int32_t precision,
+                                double tol, void* P, int64_t ldp, double* evals, double* evecs,
+                                int32_t* rank_out, void* stream) {
+  g_err.clear();
+  if (!S) return fail(PROXSDP_ERR_INVALID, "S is NULL");
+  if (n < 1 || lds < n) return fail(PROXSDP_ERR_INVALID, "need n >= 1 and lds >= n");
+  if (P && ldp < n) return fail(PROXSDP_ERR_INVALID, "ldp < n");
+  const int re = (r == 0 || r >= n) ? n : r;
+  if (r >= 0 && n > KMAX && re == n)
+    return fail(PROXSDP_ERR_UNSUPPORTED,
+                "the exact projection for n > 64 goes through rocSOLVER, which allocates; "
+                "use proxsdp_project_psd");
+  size_t need = 0;
+  int rc = proxsdp_project_workspace_size(n, r, precision, &need);
+  if (rc) return rc;
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(PROXSDP_ERR_WORKSPACE, "needs " + std::to_string(need) +
+                " bytes of scratch; the static scratch holds " +
+                std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes (use proxsdp_project_psd)");
+  if ((rc = set_lds_limits())) return rc;
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  if (!(tol > 0)) tol = 1e-12;
   return project_core(static_cast<const double*>(S), n, lds, re, tol, static_cast<double*>(P), ldp,
                       evals, evecs, rank_out, ws, static_cast<hipStream_t>(stream));
 }

@@ -12,7 +12,8 @@ import numpy as np
 from . import _lib
 from ._lib import FP64, Info, Problem, check, default_options, lib
 
-__all__ = ["Solver", "project_psd", "problem_struct", "workspace_size", "step_many"]
+__all__ = ["Solver", "project_psd", "project_psd_noalloc", "problem_struct", "workspace_size",
+           "step_many"]
 
 
 def _ptr(a: np.ndarray, ctype):
@@ -277,4 +278,27 @@ def project_psd(S, r: int, tol: float = 1e-12, want_P: bool = True, want_vectors
         C.byref(rank), C.c_void_p(ptr), int(nb.value), _stream_handle(S.device)),
         "proxsdp_project_psd")
     del buf
+    return P, evals, evecs, int(rank.value)
+
+
+def project_psd_noalloc(S, r: int, tol: float = 1e-12, P=None, want_vectors: bool = False):
+    """proxsdp_project_psd_noalloc: aproj(S, r) with the library's static
+    device scratch instead of a workspace.  ``P``: a preallocated n x n float64
+    device tensor (or None).  Returns (P, eigenvalues, eigenvectors or None,
+    number of positive kept eigenvalues)."""
+    import torch
+    assert S.is_cuda and S.dtype == torch.float64 and S.dim() == 2 and S.stride(1) == 1
+    n = S.shape[0]
+    re = n if (r <= 0 or r >= n) else r
+    if P is not None:
+        assert P.is_cuda and P.dtype == torch.float64 and P.stride(1) == 1 and P.shape[0] >= n
+    evals = np.zeros(re)
+    evecs = np.zeros((n, re)) if want_vectors else None
+    rank = C.c_int32()
+    check(lib.proxsdp_project_psd_noalloc(
+        C.c_void_p(S.data_ptr()), n, S.stride(0), int(r), FP64, float(tol),
+        C.c_void_p(P.data_ptr()) if P is not None else None, P.stride(0) if P is not None else n,
+        evals.ctypes.data_as(C.POINTER(C.c_double)),
+        evecs.ctypes.data_as(C.POINTER(C.c_double)) if evecs is not None else None,
+        C.byref(rank), _stream_handle(S.device)), "proxsdp_project_psd_noalloc")
     return P, evals, evecs, int(rank.value)
