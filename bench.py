@@ -67,8 +67,9 @@ def main():
     ap.add_argument("--window", type=int, default=0, help="Algorithm 2 window l (0 = library default)")
     ap.add_argument("--eig-rel", type=float, default=0.0, help="eigen accuracy factor (0 = default)")
     ap.add_argument("--r0", type=int, default=0, help="initial target rank (0 = default, 1)")
-    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64",
-                    help="storage of W for the timed steps (fp32 = precision form)")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16", "implicit"], default="fp64",
+                    help="storage of W for the timed steps (fp32 / bf16 = precision form, "
+                         "implicit = no dense W)")
     ap.add_argument("--workload", choices=["maxcut", "equip", "snl"], default="maxcut",
                     help="maxcut / equip: G(n, p); snl: --n sensors (2000 for the full case)")
     ap.add_argument("--progress", type=int, default=0,
@@ -128,7 +129,7 @@ def main():
         opts["time_limit_s"] = args.time_limit
     main_opts = dict(opts)
     if args.precision != "fp64":
-        main_opts["precision"] = 1 if args.precision == "fp32" else 2
+        main_opts["precision"] = {"fp32": 1, "bf16": 2, "implicit": 3}[args.precision]
     s = Solver(prob, device=dev, **main_opts)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
@@ -241,7 +242,7 @@ def main():
     # the stored layout, and of the unique entries n(n+1)/2 of the symmetric W
     # and W+ (what a triangle-only layout would have to move), over the summed
     # kernel time
-    wb = 8 if args.precision == "fp64" else (4 if args.precision == "fp32" else 2)
+    wb = {"fp64": 8, "fp32": 4, "bf16": 2, "implicit": 0}[args.precision]
     uniq = (pass_cnt + write_cnt) * prob.n * (prob.n + 1) / 2 * wb
     sweep_s = pass_s + write_s
     roofline["sweep"] = {
@@ -262,7 +263,7 @@ def main():
     prec = None
     if not args.no_precision_form and not args.iters and args.precision == "fp64":
         prec = {}
-        for name, code in (("fp32", 1), ("bf16", 2)):
+        for name, code in (("fp32", 1), ("bf16", 2), ("implicit", 3)):
             prec[name], answers[name] = precision_form(prob, dev, opts, sum(times) / len(times),
                                                        last, code)
     cpu = None
@@ -283,7 +284,8 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 W / f64 Rayleigh-Ritz",
+        "dtype": {"fp64": "f64", "implicit": "f64", "fp32": "f32 W / f64 Rayleigh-Ritz",
+                  "bf16": "bf16 W / f64 Rayleigh-Ritz"}[args.precision],
         "data": "synthetic (seeded; Erdos-Renyi graphs with unit weights, or random sensor networks)",
         "config": {
             "workload": (f"{args.workload} G({n},{args.p}) seed {args.seed}" if args.workload != "snl"
@@ -295,6 +297,12 @@ def main():
             "setup_s": round(setup_s, 3), "rank_path": s.rank_path(), "rank_X": rank_x,
             "window": args.window or 50,
             "rr_calls": int(dbg["rr_calls"]), "rr_cholesky_calls": int(dbg["rr_cholesky_calls"]),
+            "rr_cholesky_reasons": {"gram": int(dbg["rr_chol_gram"]),
+                                    "couplings": int(dbg["rr_chol_couplings"]),
+                                    "tail_bound": int(dbg["rr_chol_tail"])},
+            "verify_steps": last["verify_steps"],
+            "rr_phase_s": {"newton": round(dbg["rr_t_newton"], 4), "cholesky": round(dbg["rr_t_cholesky"], 4),
+                           "diagonalise": round(dbg["rr_t_diag"], 4), "output": round(dbg["rr_t_out"], 4)},
         },
         "roofline": roofline,
         "precision_form": prec,
@@ -384,15 +392,18 @@ def full_projection_cost(s, dev, t_lr, info):
 
 
 def precision_form(prob, dev, opts, t64, info64, code):
-    """One solve of the precision form (W stored in FP32 or BF16, filter passes
-    on FP32 / BF16 MFMA, exact FP64 Rayleigh-Ritz passes) of the same instance,
-    timed like the FP64 steps, with its error against the plain FP64 GPU answer."""
+    """One solve of another form of the same instance, timed like the FP64
+    steps (after one untimed solve), with its difference from the plain FP64
+    GPU answer: the precision form (W stored in FP32 or BF16, filter passes on
+    FP32 / BF16 MFMA, exact FP64 Rayleigh-Ritz passes) or the implicit form (no
+    dense W, FP64 throughout)."""
     import ctypes as C
     import numpy as np
     import torch
     from paper_1810_05231_amd import Solver
     from paper_1810_05231_amd._lib import check, lib
     s = Solver(prob, device=dev, precision=code, **opts)
+    s.solve()   # warm-up (code objects, graphs of the library's first calls)
     check(lib.proxsdp_reset(s._h), "proxsdp_reset")
     check(lib.proxsdp_profile_enable(s._h, 1), "profile_enable")
     torch.cuda.synchronize()
@@ -403,11 +414,15 @@ def precision_form(prob, dev, opts, t64, info64, code):
     tot = np.zeros(8)
     check(lib.proxsdp_profile_totals(s._h, tot.ctypes.data_as(C.POINTER(C.c_double)), 8),
           "profile_totals")
-    log(f"precision form ({'fp32' if code == 1 else 'bf16'}): {info['status_name']} iters={info['iters']} r={info['r']} "
-        f"passes={info['passes']} wall={dt:.3f}s obj={info['obj']:.8f}")
+    name = {1: "fp32", 2: "bf16", 3: "implicit"}[code]
+    log(f"form {name}: {info['status_name']} iters={info['iters']} r={info['r']} "
+        f"passes={info['passes']} verify={info['verify_steps']} wall={dt:.3f}s obj={info['obj']:.8f}")
+    form = ("no dense W: every pass applies W = V Lambda V^T + D + rank-one terms in FP64 "
+            "(implicit low-rank + sparse operator)" if code == 3 else
+            ("FP32" if code == 1 else "BF16") + " dense W (low-precision MFMA filter passes) "
+            "+ exact FP64 Rayleigh-Ritz passes (implicit operator)")
     out = {
-        "form": ("FP32" if code == 1 else "BF16") + " dense W (low-precision MFMA filter passes) "
-                "+ exact FP64 Rayleigh-Ritz passes (implicit operator)",
+        "form": form,
         "value": round(dt, 4), "unit": "s", "status": info["status_name"],
         "iters": info["iters"], "passes": info["passes"], "final_rank": info["r"],
         "obj": info["obj"], "rho_p": info["rho_p"], "rho_d": info["rho_d"],

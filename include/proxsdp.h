@@ -86,6 +86,16 @@ extern "C" {
 #define PROXSDP_FP64 0
 #define PROXSDP_FP32 1
 #define PROXSDP_BF16 2
+/* No dense iterate at all: every pass of the partial eigensolve applies
+ * W = X - alpha (C - M*(y)) exactly in FP64 through its structure,
+ * W B = V (Lambda (V^T B)) + D B + sum_q gamma_q u_q (u_q^T B), with X =
+ * V diag(Lambda) V^T the factors of the current iterate, D = -alpha C +
+ * alpha M*(y) on the sparsity pattern of C and the constraint rows, and the
+ * rank-one constraint terms.  O(n (r + k) k + nnz k) per pass instead of the
+ * n^2 of a dense pass, and no n x n buffer; the iterates are those of
+ * PROXSDP_FP64 up to rounding order.  For sparse / low-rank data (a C or
+ * constraint rows with O(n^2) triplets cost as much as a dense pass). */
+#define PROXSDP_IMPLICIT 3
 
 /* --------------------------------------------------------- problem */
 /* General SDP form, Section 1.3.  All pointers are host pointers. */
@@ -130,8 +140,10 @@ typedef struct {
                            on FP32 / BF16 MFMA; every Rayleigh-Ritz pass applies W
                            exactly in FP64 from the factors of X, the sparse part
                            and the rank-one terms; factors, Rayleigh-Ritz,
-                           residuals and the dual step stay FP64).  The exact
-                           small-n path (n <= 64 or full_eig) always uses FP64. */
+                           residuals and the dual step stay FP64), or
+                           PROXSDP_IMPLICIT (no dense W, every pass through the
+                           factors in FP64).  The exact small-n path (n <= 64 or
+                           full_eig) always uses a dense FP64 W.                 */
   int32_t max_iters;    /* default 200000                                        */
   double time_limit_s;  /* default 1200 (the paper's cap); <= 0 = none           */
   int32_t row_scaling;  /* 1 (default): rows scaled to unit Frobenius norm        */
@@ -187,12 +199,14 @@ typedef struct {
   int32_t verify_steps; /* exact-step convergence checks taken: once the residual
                            and rank tests pass on the partial path with the
                            adaptive eigensolve accuracy, one more iteration runs
-                           with every kept Ritz pair converged to eig_tol, and
-                           the solve stops only if that exact step's residuals
-                           meet tol; otherwise the iteration continues, with
-                           eig_rel scaled by 0.1 / (q - 1) (floor 1e-3) when the
-                           exact step's residual is q > 1.1 times the reported
-                           one                                                   */
+                           with the kept Ritz pairs converged (absolute Ritz
+                           residual <= max(eig_tol max|theta|, 0.01 alpha eps_p)),
+                           and the solve stops only if that exact step's
+                           residuals meet tol.  Otherwise the iteration
+                           continues: with the exact residual q times the
+                           reported one, the next check waits for reported
+                           residuals below tol / (1.02 q), and eig_rel is
+                           scaled by 0.1 / (q - 1) (floor 1e-3) if q > 1.1      */
 } proxsdp_info;
 
 typedef struct proxsdp_handle proxsdp_handle;
@@ -274,6 +288,23 @@ int proxsdp_saved_count(proxsdp_handle *h, int32_t *count);
 int proxsdp_get_saved(proxsdp_handle *h, int32_t idx, double *V, double *lambda, double *y,
                       int32_t *r_out, int32_t *iter_out);
 
+/* Random-hyperplane rounding (Goemans-Williamson, the rounding of the max-cut
+ * relaxation that the paper's Section 1.1 cites) of the current iterate
+ * X = V diag(lambda) V^T: for each trial t,
+ *   x_t = sign(V diag(sqrt(lambda)) g_t) in {-1, +1}^n   (+1 where the sum is >= 0)
+ * and its value <C, x_t x_t^T> (for the max-cut relaxation C = -L/4 this is
+ * minus the weight of the cut, and x_t x_t^T satisfies diag = 1).
+ *   trials  1 .. 64
+ *   g       host, trials x r row-major Gaussian vectors drawn by the caller
+ *           (r = the rank proxsdp_get_factors reports; NULL allowed if r = 0)
+ *   values  host, trials values <C, x_t x_t^T> (or NULL)
+ *   x_best  host, n entries of the trial with the smallest value (or NULL)
+ *   best    host, index of that trial (or NULL); ties go to the first
+ * Synchronises.  Errors: PROXSDP_ERR_INVALID (trials out of range, g NULL or
+ * non-finite). */
+int proxsdp_round_hyperplane(proxsdp_handle *h, int32_t trials, const double *g, double *values,
+                             int8_t *x_best, int32_t *best);
+
 /* Warm start: restarts the iteration (counters, rank control and history
  * cleared, as proxsdp_reset) from X0 = V diag(lambda) V^T and y0 instead of
  * X0 = 0, y0 = 0 (Algorithm 1 from a given point).  V: n x r row-major host
@@ -329,7 +360,12 @@ int proxsdp_rank_path(proxsdp_handle *h, int32_t *iters, int32_t *ranks, int32_t
  * half-width, 17 Jacobi sweeps, 18 Newton refinement steps of the last
  * Rayleigh-Ritz step or -1 if it took the Cholesky path, 19 number of
  * Rayleigh-Ritz steps on the Cholesky path and 20 of all Rayleigh-Ritz steps
- * since the last create/reset) followed by the Ritz values of the last
+ * since the last create/reset, 21 iteration counter, 22 / 23 / 24 Cholesky-path
+ * steps that left the Newton refinement because the Gram matrix stayed
+ * non-orthonormal / couplings among the kept pairs stayed above 1e-4 max|theta|
+ * / the bound on the unresolved tail exceeded the r-th value, 25 .. 28 seconds
+ * the Rayleigh-Ritz steps spent in their Newton refinement / Cholesky path /
+ * diagonalisation / coefficient output, from the device clock) followed by the Ritz values of the last
  * Rayleigh-Ritz step in out[64 ..] if count > 64.  Synchronises. */
 int proxsdp_debug_scalars(proxsdp_handle *h, double *out, int32_t count);
 

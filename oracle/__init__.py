@@ -23,9 +23,15 @@ Parity status per function (pins live in tests/test_oracle_*.py):
   maxcut_bracket                       pinned (exact values on K_n at the closed-
                                        form optimum, rescaled and feasible points)
   brute_force_maxcut / _min_bisection  pinned (K_n and C_n closed forms)
+  hyperplane_round, gw_expected_cut    pinned (rank-one bipartite optimum rounds
+                                       to the bipartition; every rounding at most
+                                       the brute-force max-cut; the empirical
+                                       mean of many trials matches the arccos
+                                       expectation, which is >= 0.878 x SDP)
 """
 from .sdp import *  # noqa: F401,F403
 from .sdp import (CONVERGED, MAX_ITERS, NUMERICAL, RANK_LIMIT, TIME_LIMIT, Certificate, Operators,  # noqa
                   SolveResult, aproj_psd, brute_force_maxcut, brute_force_min_bisection,
-                  certificate, dense_sym_from_coo, dual_resolvent, eig_desc, maxcut_bracket,
+                  certificate, dense_sym_from_coo, dual_resolvent, eig_desc, gw_expected_cut,
+                  hyperplane_round, maxcut_bracket,
                   pdhg_step, proj_box, proj_psd, smat, solve, svec, svec_index)

@@ -459,3 +459,27 @@ def maxcut_bracket(prob, X: np.ndarray, y: np.ndarray):
     Xf = X / np.outer(d, d)
     upper = float(np.sum(C * Xf))
     return lower, upper
+
+
+# ------------------------------------------------------ hyperplane rounding
+def hyperplane_round(V: np.ndarray, lam: np.ndarray, C: np.ndarray, G: np.ndarray):
+    """Goemans-Williamson random-hyperplane rounding (cited in Section 1.1)
+    of X = V diag(lam) V^T: trial t takes the Gaussian vector G[t] and the
+    signs x_t = sign(V diag(sqrt(lam)) G[t]) (+1 where the sum is >= 0),
+    i.e. the side of the hyperplane with normal G[t] on which each row vector
+    of the factor V sqrt(lam) lies.  Returns (x: trials x n, values
+    <C, x_t x_t^T>).  For max-cut (C = -L/4), -value is the cut weight.
+    """
+    F = V * np.sqrt(np.maximum(lam, 0.0))          # n x r factor of X
+    S = np.asarray(G, dtype=np.float64) @ F.T       # trials x n
+    x = np.where(S >= 0.0, 1.0, -1.0)
+    values = np.einsum("ti,ij,tj->t", x, C, x)
+    return x, values
+
+
+def gw_expected_cut(X: np.ndarray, edges: np.ndarray) -> float:
+    """Expected cut weight of hyperplane rounding of a unit-diagonal X
+    (Goemans and Williamson's lemma): sum over edges of arccos(X_ij) / pi."""
+    e = np.asarray(edges).reshape(-1, 2)
+    xij = np.clip(X[e[:, 0], e[:, 1]], -1.0, 1.0)
+    return float(np.sum(np.arccos(xij)) / math.pi)

@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "running", 1: "converged", 2: "max_iters", 3: "time_limit", 4
 RANK_TEST_LAMBDA_R = 0
 RANK_TEST_LAMBDA_R_PLUS_1 = 1
 
-FP64, FP32, BF16 = 0, 1, 2
+FP64, FP32, BF16, IMPLICIT = 0, 1, 2, 3
 
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)
@@ -101,6 +101,8 @@ def _load():
         "proxsdp_get_state": (C.c_int, [H, _f64p, _f64p, _f64p, _i32p]),
         "proxsdp_set_state": (C.c_int, [H, C.c_int32, _f64p, _f64p, _f64p]),
         "proxsdp_saved_count": (C.c_int, [H, _i32p]),
+        "proxsdp_round_hyperplane": (C.c_int, [H, C.c_int32, _f64p, _f64p, C.POINTER(C.c_int8),
+                                               _i32p]),
         "proxsdp_get_saved": (C.c_int, [H, C.c_int32, _f64p, _f64p, _f64p, _i32p, _i32p]),
         "proxsdp_destroy": (None, [H]),
         "proxsdp_project_workspace_size": (C.c_int, [C.c_int32, C.c_int32, C.c_int32,

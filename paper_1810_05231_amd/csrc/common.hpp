@@ -66,6 +66,13 @@ enum Scalar {
   S_RRCHOL,       // number of Rayleigh-Ritz calls that took the Cholesky path
   S_RRCOUNT,      // number of Rayleigh-Ritz calls
   S_ITER,         // iterations finalised (ring slot of the next record)
+  S_RRWHY1,       // Rayleigh-Ritz calls that left the Newton path because G stayed
+  S_RRWHY2,       //   non-orthonormal / kept couplings stayed large / the tail
+  S_RRWHY3,       //   bound exceeded the r-th value (counts since create/reset)
+  S_RRT0,         // Rayleigh-Ritz seconds (wave 0's clock, summed since create/reset):
+  S_RRT1,         //   Newton steps / Cholesky path / diagonalisation and sort /
+  S_RRT2,         //   coefficients, residual estimates and next-basis matrices
+  S_RRT3,
   S_COUNT
 };
 
@@ -109,10 +116,10 @@ struct DevProblem {
 constexpr int FAC_RES = 2 * KMAX * KMAX + MAX_R1 * KMAX;   // Ritz residual norms^2 (k values)
 constexpr int FAC_STRIDE = FAC_RES + KMAX;
 constexpr int VB_STRIDE = KMAX * KMAX + MAX_R1 * KMAX;  // per-slice partials of V^T B, u^T B
-constexpr int ROW_PART = 4;                 // eps_d^2, <dMX, dy>, dual obj, nonfinite
+constexpr int ROW_PART = 5;                 // eps_d^2, <dMX, dy>, dual obj, nonfinite, <y, M(X+)>
 constexpr int ROW_LANES = 8;                // threads per constraint row in the dual step
 constexpr int ROWS_PER_BLOCK = 256 / ROW_LANES;
-constexpr int PAT_PART = 4 + MAX_R1;        // min gersh, ||M*dy||^2 (sparse), obj, unused, cross_q
+constexpr int PAT_PART = 4 + MAX_R1;        // min gersh, ||M*dy||^2 (sparse), unused x2, cross_q
 
 // Number of SLICE-row workgroups covering npad rows.
 inline int n_slices(int npad) { return (npad + SLICE - 1) / SLICE; }

@@ -490,7 +490,16 @@ __global__ __launch_bounds__(512) void k_rowwise(const double* __restrict__ B,
 //   k_sum_vb         slice sums, scaled by lambda_t and gamma_q
 //   k_implicit_rows  Z_i = V_i M + sum_q u_q[i] M_q + sum_{e in row i} D_e B_other(e)
 // and the Rayleigh-Ritz Gram partials come from k_reduce_gram on Z.
+__device__ inline int last_positive(const double* lam, int r) {
+  // number of leading factor columns that can contribute: the index after
+  // the last positive lambda (r <= KMAX, one lane per column)
+  const int ln = threadIdx.x & 63;
+  const unsigned long long pos = __ballot(ln < r && lam[ln < r ? ln : 0] > 0.0);
+  return pos ? 64 - __clzll((long long)pos) : 0;
+}
+
 __global__ __launch_bounds__(256) void k_vtb(const double* __restrict__ V, int r,
+                                             const double* __restrict__ lam,
                                              const double* __restrict__ B, int k, int n_r1,
                                              const double* __restrict__ r1_u, int npad,
                                              double* __restrict__ vb_part) {
@@ -498,17 +507,25 @@ __global__ __launch_bounds__(256) void k_vtb(const double* __restrict__ V, int r
   const int i0 = s * SLICE;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int m = lane & 15, kq = lane >> 4;
+  // columns after the last positive lambda are zero in X; their rows of
+  // V^T B are never read (k_sum_vb and k_implicit_rows stop there too)
+  r = last_positive(lam, r);
   const int rb = (r + 15) / 16, kb = k / 16;
   double* out = vb_part + (int64_t)s * VB_STRIDE;
   for (int blk = wave; blk < rb * kb; blk += nw) {
     const int a0 = (blk / kb) * 16, b0 = (blk - (blk / kb) * kb) * 16;
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-    for (int q0 = 0; q0 < SLICE; q0 += 4) {
-      const int row = i0 + q0 + kq;
-      const double a = (a0 + m < r) ? V[(int64_t)row * KMAX + a0 + m] : 0.0;
-      const double b = B[(int64_t)row * k + b0 + m];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    // all operands of the block's 16 MFMAs are loaded before the first one
+    double av[SLICE / 4], bv[SLICE / 4];
+#pragma unroll
+    for (int q = 0; q < SLICE / 4; ++q) {
+      const int row = i0 + 4 * q + kq;
+      av[q] = (a0 + m < r) ? V[(int64_t)row * KMAX + a0 + m] : 0.0;
+      bv[q] = B[(int64_t)row * k + b0 + m];
     }
+#pragma unroll
+    for (int q = 0; q < SLICE / 4; ++q)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int ra = a0 + kq + 4 * v;
@@ -530,6 +547,7 @@ __global__ __launch_bounds__(256) void k_sum_vb(const double* __restrict__ vb_pa
                                                 int r, int k, DevProblem dp,
                                                 const double* __restrict__ y, int lam_off,
                                                 double* __restrict__ small) {
+  r = last_positive(small + lam_off, r);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int n1 = r * k;
   if (t >= n1 + dp.n_r1 * k) return;
@@ -554,7 +572,8 @@ __global__ __launch_bounds__(256) void k_sum_vb(const double* __restrict__ vb_pa
 //   Z_i = sum_t V_it M_t + sum_q u_q[i] M_q + sum_{e in row i} D_e B_other(e)
 // with M from k_sum_vb.  A workgroup covers 4 rows, a thread one column.
 __global__ __launch_bounds__(256) void k_implicit_rows(DevProblem dp, const double* __restrict__ V,
-                                                       int r, const double* __restrict__ small,
+                                                       int r, int lam_off,
+                                                       const double* __restrict__ small,
                                                        const double* __restrict__ dval,
                                                        const double* __restrict__ B, int k,
                                                        double* __restrict__ Z) {
@@ -564,6 +583,7 @@ __global__ __launch_bounds__(256) void k_implicit_rows(DevProblem dp, const doub
   const int c = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= dp.npad) return;   // whole waves
+  r = last_positive(small + lam_off, r);
   double acc = 0.0;
   if (i < dp.n) {
     if (c < k) {
@@ -712,6 +732,9 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
   const int J = I + (idx - first(I));
   const int tile_id = I * T + J;
   const int a0 = I * TILE, b0 = J * TILE;
+  const double* lam = small + lam_off;
+  // factor columns after the last positive lambda add nothing to the tile
+  r = last_positive(lam, r);
   const int nq = rank1 ? dp.n_r1 : 0;
   const int rr = r + nq;
   // LDS: first the scaled factor rows of the column block (64 x rr, odd row
@@ -724,7 +747,6 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
   auto tix = [](int a, int c) { return a * TILE + (c ^ a); };
   double* sVb = sm;
   double* sT = sm;
-  const double* lam = small + lam_off;
   const double alpha = small[SL::SC + S_ALPHA];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;

@@ -25,6 +25,7 @@
 #include "../../include/proxsdp.h"
 #include "common.hpp"
 #include "dense.hpp"
+#include "rounding.hpp"
 #include "small.hpp"
 #include "sparse.hpp"
 
@@ -119,8 +120,10 @@ int validate(const proxsdp_problem* pb, const proxsdp_options* o) {
     if (!(o->tol > 0)) return fail(PROXSDP_ERR_INVALID, "tol must be > 0");
     if (o->check_every < 1 || o->window < o->check_every || o->window % o->check_every)
       return fail(PROXSDP_ERR_INVALID, "window must be a positive multiple of check_every");
-    if (o->precision != PROXSDP_FP64 && o->precision != PROXSDP_FP32 && o->precision != PROXSDP_BF16)
-      return fail(PROXSDP_ERR_INVALID, "precision must be PROXSDP_FP64, PROXSDP_FP32 or PROXSDP_BF16");
+    if (o->precision != PROXSDP_FP64 && o->precision != PROXSDP_FP32 && o->precision != PROXSDP_BF16 &&
+        o->precision != PROXSDP_IMPLICIT)
+      return fail(PROXSDP_ERR_INVALID,
+                  "precision must be PROXSDP_FP64, PROXSDP_FP32, PROXSDP_BF16 or PROXSDP_IMPLICIT");
     if (o->alpha < 0) return fail(PROXSDP_ERR_INVALID, "alpha must be >= 0");
     if (o->full_eig && pb->n > KMAX)
       return fail(PROXSDP_ERR_UNSUPPORTED, "full_eig needs n <= " + std::to_string(KMAX));
@@ -471,6 +474,10 @@ struct proxsdp_handle {
   double *y = nullptr, *y_old = nullptr, *MX = nullptr, *MX_old = nullptr;
   double *row_part = nullptr, *pat_part = nullptr, *dval = nullptr;
   IterRecord* ring = nullptr;
+  double* round_g = nullptr;        // hyperplane rounding: Gaussian vectors (trials x r)
+  signed char* round_x = nullptr;   //   signs (n x trials)
+  double* round_part = nullptr;     //   per-block partial values
+  double* round_val = nullptr;      //   values <C, x x^T> per trial
   // control
   int iters = 0, passes = 0, rank_updates = 0;
   int m_rounds = 2;
@@ -481,6 +488,8 @@ struct proxsdp_handle {
   double eps_lambda = 0;
   double rank_value = std::nan("");   // last confirmed rank-test value (upper estimate)
   int verify_steps = 0;               // exact-step convergence checks taken
+  double verify_q = 1.0;              // last failed check: exact / reported residual
+  double strict_tol = 0.0;            // eigensolve target of the strict rounds (0: eig_tol)
   double eig_rel_user = 0.2;          // eig_rel as created (the checks may lower it)
   // Algorithm 2's intermediate feasible solutions X_[r] (host copies)
   struct Saved {
@@ -542,18 +551,24 @@ static size_t carve(proxsdp_handle* H, void* ws) {
   if (H->prec == PROXSDP_FP64) {
     H->W = c.take<double>((size_t)npad * npad);
     H->Wl = nullptr;
+  } else if (H->prec == PROXSDP_IMPLICIT) {
+    H->W = nullptr;   // no dense iterate: every pass applies W through the factors
+    H->Wl = nullptr;
   } else {
     H->W = nullptr;
     H->Wl = c.take<char>((size_t)npad * npad * H->wbytes);
   }
   // low-precision copy of the basis block (precision form's dense passes)
-  H->Bl = H->prec == PROXSDP_FP64 ? nullptr : c.take<float>((size_t)npad * H->k_cap);
+  H->Bl = (H->prec == PROXSDP_FP32 || H->prec == PROXSDP_BF16)
+              ? c.take<float>((size_t)npad * H->k_cap) : nullptr;
   H->vb_part = c.take<double>((size_t)std::max(H->nsl, 1) * VB_STRIDE);
   H->B[0] = c.take<double>((size_t)npad * H->k_cap);
   H->B[1] = c.take<double>((size_t)npad * H->k_cap);
   H->B[2] = c.take<double>((size_t)npad * H->k_cap);
   H->Z = c.take<double>((size_t)npad * H->k_cap);
-  H->part = c.take<double>((size_t)H->ch.nchunks * npad * H->k_cap);
+  // split-K partials of the dense passes (none without a dense iterate)
+  H->part = H->prec == PROXSDP_IMPLICIT ? nullptr
+                                        : c.take<double>((size_t)H->ch.nchunks * npad * H->k_cap);
   H->gram_part = c.take<double>((size_t)H->nsl * 3 * H->k_cap * H->k_cap);
   H->small = c.take<double>(SL::TOTAL);
   H->V[0] = c.take<double>((size_t)npad * KMAX);
@@ -567,6 +582,10 @@ static size_t carve(proxsdp_handle* H, void* ws) {
   H->pat_part = c.take<double>((size_t)H->npat_blocks * PAT_PART);
   H->dval = c.take<double>(h.pat_a.size());
   H->ring = c.take<IterRecord>(RING);
+  H->round_g = c.take<double>((size_t)ROUND_MAX_TRIALS * KMAX);
+  H->round_x = c.take<signed char>((size_t)npad * ROUND_MAX_TRIALS);
+  H->round_part = c.take<double>((size_t)ROUND_BLOCKS * ROUND_MAX_TRIALS);
+  H->round_val = c.take<double>(ROUND_MAX_TRIALS);
   // problem data
   DevProblem& d = H->dp;
   d.pat_a = c.take<int>(h.pat_a.size());
@@ -598,7 +617,8 @@ static void setup_dims(proxsdp_handle* H) {
   H->full = H->opt.full_eig || h.n <= KMAX;
   // the exact small-n path reads W in FP64
   H->prec = H->full ? PROXSDP_FP64 : H->opt.precision;
-  H->wbytes = H->prec == PROXSDP_FP64 ? 8 : (H->prec == PROXSDP_FP32 ? 4 : 2);
+  H->wbytes = H->prec == PROXSDP_FP64 ? 8
+             : (H->prec == PROXSDP_FP32 ? 4 : (H->prec == PROXSDP_BF16 ? 2 : 0));
   if (H->full) {
     H->r_cap = h.n;
     H->k_cap = 16;
@@ -821,14 +841,14 @@ static void launch_implicit(proxsdp_handle* H, const double* B, double* Z, bool 
   const int pp = 1 - (H->iters & 1);       // factors of the current X
   const int r = H->r_old;
   const int k = H->k;
-  hipLaunchKernelGGL(k_vtb, dim3(H->nsl), dim3(256), 0, st, H->V[pp], r, B, k, H->dp.n_r1,
-                     H->dp.r1_u, H->npad, H->vb_part);
+  hipLaunchKernelGGL(k_vtb, dim3(H->nsl), dim3(256), 0, st, H->V[pp], r, H->small + lam_slot(pp), B,
+                     k, H->dp.n_r1, H->dp.r1_u, H->npad, H->vb_part);
   const int cnt = (r + H->dp.n_r1) * k;
   if (cnt > 0)
     hipLaunchKernelGGL(k_sum_vb, dim3((cnt + 255) / 256), dim3(256), 0, st, H->vb_part, H->nsl, r,
                        k, H->dp, H->y, lam_slot(pp), H->small);
   hipLaunchKernelGGL(k_implicit_rows, dim3(H->npad / 4), dim3(256), 0, st, H->dp, H->V[pp], r,
-                     H->small, H->dval, B, k, Z);
+                     lam_slot(pp), H->small, H->dval, B, k, Z);
   // Gram partials [B^T B, B^T Z, Z^T Z] per slice (a one-chunk reduction of Z)
   if (grams) launch_reduce(Z, 1, nullptr, B, nullptr, H->npad, k, H->gram_part, 0, 0.0, 1.0, true, st);
 }
@@ -838,7 +858,7 @@ static void launch_implicit(proxsdp_handle* H, const double* B, double* Z, bool 
 // pass needs it (from the factors of the current X, the sparse part and the
 // rank-one terms, as the fused write at the end of an iteration would).
 static void ensure_w_fresh(proxsdp_handle* H) {
-  if (H->prec == PROXSDP_FP64 || H->w_fresh) return;
+  if (H->prec == PROXSDP_FP64 || H->prec == PROXSDP_IMPLICIT || H->w_fresh) return;
   const int pp = 1 - (H->iters & 1);
   const int r = H->r_old;
   prof_mark(H, H->ev_write, H->n_write, true);
@@ -908,7 +928,7 @@ static void eig_iteration(proxsdp_handle* H, int par, int m) {
   for (int j = 0; j < m - 1; ++j) {
     int nxt = 0;
     while (nxt == cur || nxt == prev) ++nxt;
-    if (H->prec == PROXSDP_BF16 && H->eta < BF16_ETA_FLOOR) {
+    if (H->prec == PROXSDP_IMPLICIT || (H->prec == PROXSDP_BF16 && H->eta < BF16_ETA_FLOOR)) {
       // exact filter pass: Z = W B from the factors, then the Chebyshev step
       launch_implicit(H, H->B[cur], H->Z, false);
       launch_reduce(H->Z, 1, H->B[nxt], H->B[cur], prev >= 0 ? H->B[prev] : nullptr, H->npad,
@@ -948,8 +968,8 @@ static void eig_iteration(proxsdp_handle* H, int par, int m) {
 
 static void pattern_and_write(proxsdp_handle* H, int par, int ring_slot) {
   hipStream_t st = H->st;
-  hipLaunchKernelGGL(k_pattern, dim3(H->npat_blocks), dim3(256), 0, st, H->dp, H->V[par], H->r,
-                     H->small, lam_slot(par), H->y, H->y_old, H->dval, H->pat_part, 1);
+  hipLaunchKernelGGL(k_pattern, dim3(H->npat_blocks), dim3(256), 0, st, H->dp, H->y, H->y_old,
+                     H->small, H->dval, H->pat_part);
   FinArgs f{};
   f.fac_part = H->fac_part;
   f.nslices = H->full ? 1 : H->nsl;
@@ -987,11 +1007,12 @@ static void iterate_once(proxsdp_handle* H) {
     H->passes += 1;
   } else if (H->opt.eig_strict) {
     // rounds until the kept Ritz pairs meet eig_tol, then one final round
+    const double target = H->strict_tol > 0 ? H->strict_tol : H->opt.eig_tol;
     for (int rd = 0; rd < 200; ++rd) {
       eig_round(H, par, false);
       double mr = 1.0;
       if (true_maxres(H, H->r, &mr)) break;
-      if (mr <= H->opt.eig_tol) break;
+      if (mr <= target) break;
     }
     eig_round(H, par, true);
   } else {
@@ -1195,17 +1216,24 @@ static int rank_probe(proxsdp_handle* H, double thr, int* verdict, double* ub_ou
 }
 
 // One PDHG iteration whose partial eigensolve runs until the kept Ritz pairs
-// meet eig_tol (the eig_strict schedule), i.e. the exact step of Algorithm 1
+// are converged (the eig_strict schedule), i.e. the exact step of Algorithm 1
 // from the current (X, y) once the rank test has shown that r covers every
 // positive eigenvalue.  Its residuals are those of an exact step, which is
 // what decides convergence (Section 2.2: the fixed point of the exact
 // iteration is the KKT point); the adaptive-accuracy iterations before it
-// only report residuals of their own inexact steps.  *out gets its record.
-static int verify_step(proxsdp_handle* H, IterRecord* out) {
+// only report residuals of their own inexact steps.  The eigen error only
+// has to be small against the step: an error delta in X moves eps_p by about
+// delta / alpha, so the absolute Ritz residual of the kept pairs is held at
+// 1% of alpha eps_p (or eig_tol, if larger).  *out gets its record.
+static int verify_step(proxsdp_handle* H, const IterRecord& last, IterRecord* out) {
   const int strict = H->opt.eig_strict;
   H->opt.eig_strict = 1;
+  H->strict_tol = last.normw > 0
+                      ? std::max(H->opt.eig_tol, 0.01 * H->opt.alpha * last.eps_p / last.normw)
+                      : H->opt.eig_tol;
   iterate_once(H);
   H->opt.eig_strict = strict;
+  H->strict_tol = 0.0;
   std::vector<IterRecord> recs;
   int rc = read_records(H, H->iters - 1, 1, recs);
   if (rc) return rc;
@@ -1269,7 +1297,9 @@ static int control(proxsdp_handle* H) {
   const int L = H->opt.window / ce;
   if (nonfinite != 0.0 || !std::isfinite(comb)) {
     H->status = PROXSDP_STATUS_NUMERICAL;
-  } else if (std::max(rho_p, rho_d) <= H->opt.tol) {
+  } else if (std::max(rho_p, rho_d) <= H->opt.tol / H->verify_q) {
+    // (verify_q > 1 after an exact-step check found the reported residuals
+    // that much below the exact ones: wait until they are low enough to pass.)
     // Algorithm 2: converged residuals stop the solve only if the rank test
     // (n - r) max(lambda, 0) <= eps_lambda passes; otherwise X_[r] is kept and
     // r doubles (at the cap the solve stops with a status saying so).
@@ -1295,7 +1325,7 @@ static int control(proxsdp_handle* H) {
     if (verdict == RANK_PASS && !H->full && !H->opt.eig_strict) {
       // the residuals above are those of an inexact step: decide on an exact one
       IterRecord vr{};
-      const int rc4 = verify_step(H, &vr);
+      const int rc4 = verify_step(H, rec, &vr);
       if (rc4) return rc4;
       const double vp = vr.eps_p / (1.0 + H->h.norm_c), vd = vr.eps_d / (1.0 + H->h.norm_rhs);
       if (std::max(vp, vd) <= H->opt.tol && std::isfinite(vp + vd)) {
@@ -1310,6 +1340,7 @@ static int control(proxsdp_handle* H) {
       const double q = std::max(vp, vd) / std::max(std::max(rho_p, rho_d), 1e-300);
       if (q > 1.1)
         H->opt.eig_rel = std::max(H->opt.eig_rel * std::min(1.0, 0.1 / (q - 1.0)), 1e-3);
+      if (std::isfinite(q)) H->verify_q = std::max(H->verify_q, 1.02 * q);
       H->hist.push_back(vr.eps_p + vr.eps_d);
     } else if (verdict == RANK_PASS) {
       H->status = PROXSDP_STATUS_CONVERGED;
@@ -1382,7 +1413,7 @@ static int reset_buffers(proxsdp_handle* H) {
   hipStream_t st = H->st;
   if (H->prec == PROXSDP_FP64)
     zero(H->W, (size_t)H->npad * H->npad, st);
-  else
+  else if (H->Wl)
     zero(static_cast<double*>(H->Wl), (size_t)H->npad * H->npad * H->wbytes / 8, st);
   zero(H->B[0], (size_t)H->npad * H->k_cap, st);
   zero(H->B[1], (size_t)H->npad * H->k_cap, st);
@@ -1415,6 +1446,8 @@ static int reset_buffers(proxsdp_handle* H) {
   H->saved.clear();
   H->rank_value = std::nan("");
   H->verify_steps = 0;
+  H->verify_q = 1.0;
+  H->strict_tol = 0.0;
   H->opt.eig_rel = H->eig_rel_user;
   H->time_s = 0;
   H->last = proxsdp_info{};
@@ -1813,6 +1846,46 @@ int proxsdp_get_saved(proxsdp_handle* H, int32_t idx, double* V, double* lambda,
   if (V && sv.r > 0) std::memcpy(V, sv.V.data(), (size_t)H->n * sv.r * sizeof(double));
   if (lambda && sv.r > 0) std::memcpy(lambda, sv.lam.data(), (size_t)sv.r * sizeof(double));
   if (y) std::memcpy(y, sv.y.data(), (size_t)H->rows * sizeof(double));
+  return PROXSDP_OK;
+}
+
+int proxsdp_round_hyperplane(proxsdp_handle* H, int32_t trials, const double* g, double* values,
+                             int8_t* x_best, int32_t* best) {
+  g_err.clear();
+  if (!H) return fail(PROXSDP_ERR_INVALID, "handle is NULL");
+  if (trials < 1 || trials > ROUND_MAX_TRIALS)
+    return fail(PROXSDP_ERR_INVALID, "trials must be in [1, " + std::to_string(ROUND_MAX_TRIALS) + "]");
+  const int r = H->r_old;
+  if (r > 0 && !g) return fail(PROXSDP_ERR_INVALID, "g is NULL");
+  if (g)
+    for (int64_t t = 0; t < (int64_t)trials * r; ++t)
+      if (!std::isfinite(g[t])) return fail(PROXSDP_ERR_INVALID, "g has a non-finite entry");
+  hipStream_t st = H->st;
+  const int par = (H->iters - 1) & 1;
+  const int n = H->n;
+  if (r > 0)
+    HIP_OK(hipMemcpyAsync(H->round_g, g, (size_t)trials * r * sizeof(double), hipMemcpyHostToDevice, st));
+  const int64_t cnt = (int64_t)n * trials;
+  hipLaunchKernelGGL(k_round_signs, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, H->V[par], r,
+                     H->small + lam_slot(par), H->round_g, trials, n, H->round_x);
+  hipLaunchKernelGGL(k_round_values, dim3(ROUND_BLOCKS), dim3(256), 0, st, H->dp, H->round_x, trials,
+                     H->round_part);
+  hipLaunchKernelGGL(k_round_reduce, dim3(1), dim3(64), 0, st, H->round_part, ROUND_BLOCKS, trials,
+                     H->round_val);
+  std::vector<double> val(trials);
+  HIP_OK(hipMemcpyAsync(val.data(), H->round_val, trials * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  int b = 0;
+  for (int t = 1; t < trials; ++t)
+    if (val[t] < val[b]) b = t;
+  if (values) std::memcpy(values, val.data(), trials * sizeof(double));
+  if (best) *best = b;
+  if (x_best) {
+    std::vector<signed char> xs((size_t)n * trials);
+    HIP_OK(hipMemcpyAsync(xs.data(), H->round_x, xs.size(), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) x_best[i] = xs[(size_t)i * trials + b];
+  }
   return PROXSDP_OK;
 }
 

@@ -660,8 +660,13 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
     d[t] = (g > 0.0) ? 1.0 / sqrt(g) : 1.0;
   }
   if (tid == 0) { flag[0] = 0; flag[1] = 0; }
+  // phase clock (constant-rate counter, 100 MHz): start, Newton steps done,
+  // Cholesky path done, projected matrix diagonalised, coefficients out
+  unsigned long long tph[5];
+  tph[0] = wall_clock64();
   __syncthreads();
   int sweeps = 0, path = -1;
+  int why = 0;   // Cholesky path taken because: 1 G not orthonormal, 2 kept couplings, 3 tail bound
   double* Sbuf;   // sorted Ritz coefficients (k x ld)
   double* Pbuf;   // P (k x ld)
   double* Ybuf;   // P S (k x ld)
@@ -756,6 +761,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
       __syncthreads();
     }
     newton_ok = offR <= fmax(1e-12, rtol) && offS <= 1e-4 * smax;
+    if (!newton_ok) why = (offR <= fmax(1e-12, rtol)) ? 2 : 1;
     if (newton_ok) {
       // re-rank on the final values; the kept couplings are re-measured on
       // that set, and the unwanted tail, not diagonalised, may hide an
@@ -780,9 +786,11 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
       const double thr = fmax(*mu_r, 0.0);
       block_sum2_max1(aS, z1, gb, red);   // sum over the kept pairs, max(gb, 0) over the tail
       newton_ok = gb <= thr && sqrt(aS) <= 1e-4 * smax;
+      if (!newton_ok) why = (gb <= thr) ? 2 : 3;
     }
     if (newton_ok) path = st;
   }
+  tph[1] = wall_clock64();
   // -------------------------------------------------------- Cholesky path
   if (!newton_ok) {
     double* L = B0;
@@ -849,6 +857,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
     }
     __syncthreads();
   }
+  tph[2] = wall_clock64();
   // symmetrise the projected matrix (B1)
   RR_FOR_KK(t, i, j) {
     if (i < j) {
@@ -866,6 +875,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
   else   // B3 (free on this path) is the second buffer
     sweeps = jacobi_eig_db(B1, B3, ld, B2, ld, k, 40, jac_tol, red, &Aeig);
   sort_desc(Aeig, ld, k, vals, perm);
+  tph[3] = wall_clock64();
   if (newton_ok) {
     // coefficients D X U[:, perm] into B0 (X^T G X is no longer needed)
     strip_mm(B0, ld, B3, ld, B2, ld, perm, d, k);
@@ -974,6 +984,9 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
       sc[S_SWEEPS] = (double)sweeps;
       sc[S_RRPATH] = (double)path;
       sc[S_RRCHOL] += (path < 0) ? 1.0 : 0.0;
+      if (why > 0) sc[S_RRWHY1 + why - 1] += 1.0;
+      tph[4] = wall_clock64();
+      for (int ph = 0; ph < 4; ++ph) sc[S_RRT0 + ph] += 1e-8 * (double)(tph[ph + 1] - tph[ph]);
       sc[S_RRCOUNT] += 1.0;
       if (bad) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 1.0);
     }

@@ -8,10 +8,9 @@
 //              and per-block sums for the dual residual of Section 2.2.
 // pattern      values D_e = -alpha C_e + alpha M*(y+)_e on the sparsity
 //              pattern (consumed by the dense write), the Gershgorin lower
-//              bound of D, the sparse part of ||M*(y+ - y)||_F^2, and the
-//              objective <C, X+> gathered from the factors.
+//              bound of D and the sparse part of ||M*(y+ - y)||_F^2.
 // finalize     combines the partial sums into eps_primal, eps_dual (Section
-//              2.2) and the iteration record.
+//              2.2), the objective and the iteration record.
 #pragma once
 
 #include "common.hpp"
@@ -28,6 +27,28 @@ __device__ inline double block_sum(double v, double* red) {
   const int nw = (blockDim.x + 63) >> 6;
   for (int w = 0; w < nw; ++w) s += red[w];
   return s;
+}
+
+// Sums of N values over the workgroup with one pair of barriers (each value
+// in the same order as block_sum: wave butterfly, then the waves in order).
+template <int N>
+__device__ inline void block_sum_many(double* v, double* red) {
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+    for (int o = 32; o > 0; o >>= 1) v[j] += __shfl_xor(v[j], o);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < N; ++j) red[wave * N + j] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w * N + j];
+    v[j] = s;
+  }
 }
 
 __device__ inline double block_min(double v, double* red) {
@@ -71,7 +92,7 @@ __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double
   // ROW_LANES) of every entry of the row, then a shuffle reduction
   const int sub = threadIdx.x % ROW_LANES;
   const int i = blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / ROW_LANES;
-  double ed2 = 0.0, cross = 0.0, dobj = 0.0, bad = 0.0;
+  double ed2 = 0.0, cross = 0.0, dobj = 0.0, bad = 0.0, ymx = 0.0;
   double mx = 0.0;
   if (i < dp.rows) {
     for (int e = dp.row_ptr[i]; e < dp.row_ptr[i + 1]; ++e) {
@@ -105,6 +126,7 @@ __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double
     ed2 = rd * rd;
     cross = dmx * dy;
     dobj = dp.rhs[i] * u;
+    ymx = y0 * mx;   // <y, M(X+)> with the y that built the projected matrix
     if (!isfinite(u) || !isfinite(mx)) bad = 1.0;
     y_old[i] = y0;
     y[i] = u;
@@ -115,9 +137,10 @@ __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double
   cross = block_sum(cross, red);
   dobj = block_sum(dobj, red);
   bad = block_sum(bad, red);
+  ymx = block_sum(ymx, red);
   if (threadIdx.x == 0) {
     double* o = row_part + (int64_t)blockIdx.x * ROW_PART;
-    o[0] = ed2; o[1] = cross; o[2] = dobj; o[3] = bad;
+    o[0] = ed2; o[1] = cross; o[2] = dobj; o[3] = bad; o[4] = ymx;
   }
 }
 
@@ -127,82 +150,56 @@ __device__ inline double wave_sum(double v) {
 }
 
 // One wave per row a of the symmetric pattern (rows strided over the grid);
-// lanes split the row's entries.  The objective term of the row,
-//   sum over owned entries e = (a, b) of w_e C_e X+_ab
-//     = sum_t lambda_t V_at g_t,   g_t = sum_e w_e C_e V_bt,
-// is formed with lanes over t: each entry's b and w_e C_e are broadcast from
-// the lane that holds it and the wave reads factor row b coalesced.
-__global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __restrict__ V, int r,
-                                                 const double* __restrict__ small, int lam_off,
-                                                 const double* __restrict__ y,
+// lanes split the row's entries.
+__global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __restrict__ y,
                                                  const double* __restrict__ y_old,
+                                                 const double* __restrict__ small,
                                                  double* __restrict__ dval,
-                                                 double* __restrict__ pat_part, int with_obj) {
+                                                 double* __restrict__ pat_part) {
   __shared__ double red[16];
-  const double* lam = small + lam_off;
   const double alpha = small[SL::SC + S_ALPHA];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  double lo = 1e308, mdy2 = 0.0, obj = 0.0;
+  double lo = 1e308, mdy2 = 0.0;
   double crossq[MAX_R1];
   for (int q = 0; q < MAX_R1; ++q) crossq[q] = 0.0;
   for (int a = blockIdx.x * 4 + wave; a < dp.n; a += gridDim.x * 4) {
     double center = 0.0, radius = 0.0;
-    double g = 0.0;   // lane t: sum over the owned entries of w_e C_e V_bt
     const int s0 = dp.sym_ptr[a], s1 = dp.sym_ptr[a + 1];
-    for (int base = s0; base < s1; base += 64) {
-      const int s = base + lane;
-      double wc = 0.0;
-      int bb = 0;
-      if (s < s1) {
-        const int e = dp.sym_e[s];
-        const int ea = dp.pat_a[e], eb = dp.pat_b[e];
-        const double ce = dp.pat_c[e];
-        double dv = -alpha * ce;
-        double md = 0.0;
-        for (int t = dp.pat_rptr[e]; t < dp.pat_rptr[e + 1]; ++t) {
-          const int i = dp.pat_row[t];
-          const double v = dp.pat_val[t];
-          const double yi = y[i];
-          dv += alpha * yi * v;
-          md += (yi - y_old[i]) * v;
-        }
-        if (ea == eb)
-          center += dv;
-        else
-          radius += fabs(dv);
-        if (ea == a) {  // owner of the entry
-          dval[e] = dv;
-          const double w = (ea == eb) ? 1.0 : 2.0;
-          mdy2 += w * md * md;
-          for (int q = 0; q < dp.n_r1; ++q)
-            crossq[q] += w * md * dp.r1_u[(int64_t)q * dp.npad + ea] * dp.r1_u[(int64_t)q * dp.npad + eb];
-          wc = w * ce;
-          bb = eb;
-        }
+    for (int s = s0 + lane; s < s1; s += 64) {
+      const int e = dp.sym_e[s];
+      const int ea = dp.pat_a[e], eb = dp.pat_b[e];
+      double dv = -alpha * dp.pat_c[e];
+      double md = 0.0;
+      for (int t = dp.pat_rptr[e]; t < dp.pat_rptr[e + 1]; ++t) {
+        const int i = dp.pat_row[t];
+        const double v = dp.pat_val[t];
+        const double yi = y[i];
+        dv += alpha * yi * v;
+        md += (yi - y_old[i]) * v;
       }
-      if (with_obj) {
-        const int cnt = min(64, s1 - base);
-#pragma unroll 8
-        for (int j = 0; j < cnt; ++j) {
-          const double wcj = __shfl(wc, j);
-          const int bj = __shfl(bb, j);
-          if (wcj != 0.0 && lane < r) g += wcj * V[(int64_t)bj * KMAX + lane];
-        }
+      if (ea == eb)
+        center += dv;
+      else
+        radius += fabs(dv);
+      if (ea == a) {  // owner of the entry
+        dval[e] = dv;
+        const double w = (ea == eb) ? 1.0 : 2.0;
+        mdy2 += w * md * md;
+        for (int q = 0; q < dp.n_r1; ++q)
+          crossq[q] += w * md * dp.r1_u[(int64_t)q * dp.npad + ea] * dp.r1_u[(int64_t)q * dp.npad + eb];
       }
     }
-    if (with_obj && lane < r) obj += lam[lane] * V[(int64_t)a * KMAX + lane] * g;
     center = wave_sum(center);
     radius = wave_sum(radius);
     lo = fmin(lo, center - radius);
   }
   lo = block_min(lo, red);
   mdy2 = block_sum(mdy2, red);
-  obj = block_sum(obj, red);
   for (int q = 0; q < MAX_R1; ++q) crossq[q] = block_sum(crossq[q], red);
   if (threadIdx.x == 0) {
     double* o = pat_part + (int64_t)blockIdx.x * PAT_PART;
-    o[0] = lo; o[1] = mdy2; o[2] = obj; o[3] = 0.0;
+    o[0] = lo; o[1] = mdy2; o[2] = 0.0; o[3] = 0.0;
     for (int q = 0; q < MAX_R1; ++q) o[4 + q] = crossq[q];
   }
 }
@@ -211,6 +208,11 @@ __global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __
 //   ||X+ - X||^2 = ||X+||^2 + ||X||^2 - 2 <X+, X> from the factor Grams,
 //   eps_p^2 = ||dX||^2 / alpha^2 + (2/alpha) <M(dX), dy> + ||M*(dy)||^2,
 //   eps_d^2 = sum (dy/alpha + M(dX))^2     (Section 2.2, sign of Section 1.3).
+// The objective <C, X+> comes from the projected matrix W = X - alpha (C -
+// M*(y)): X+ = V diag(lambda) V^T with v_t^T W v_t = theta_t (Rayleigh-Ritz,
+// or the exact eigenpairs), so <W, X+> = sum_t lambda_t theta_t and
+//   <C, X+> = (<X, X+> + alpha <y, M(X+)> - sum_t lambda_t theta_t) / alpha,
+// with <X, X+> from the factor Grams and <y, M(X+)> from the dual step.
 __device__ void finalize_iteration(const FinArgs& f, double* small, const DevProblem& dp,
                                    const double* y, const double* y_old, double* red) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -230,29 +232,29 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
       x01 += lam[a] * lam0[b] * g * g;
     }
   }
-  double ed2 = 0.0, cross = 0.0, dobj = 0.0, bad = 0.0;
+  double ed2 = 0.0, cross = 0.0, dobj = 0.0, bad = 0.0, ymx = 0.0;
   for (int b = tid; b < f.nrow_blocks; b += nt) {
     const double* o = f.row_part + (int64_t)b * ROW_PART;
-    ed2 += o[0]; cross += o[1]; dobj += o[2]; bad += o[3];
+    ed2 += o[0]; cross += o[1]; dobj += o[2]; bad += o[3]; ymx += o[4];
   }
-  double lo = 1e308, mdy2 = 0.0, obj = 0.0;
+  double lo = 1e308, mdy2 = 0.0, lth = 0.0;
   double cq[MAX_R1];
   for (int q = 0; q < MAX_R1; ++q) cq[q] = 0.0;
   for (int b = tid; b < f.npat_blocks; b += nt) {
     const double* o = f.pat_part + (int64_t)b * PAT_PART;
-    lo = fmin(lo, o[0]); mdy2 += o[1]; obj += o[2];
+    lo = fmin(lo, o[0]); mdy2 += o[1];
     for (int q = 0; q < MAX_R1; ++q) cq[q] += o[4 + q];
   }
-  x2 = block_sum(x2, red);
-  x01 = block_sum(x01, red);
-  ed2 = block_sum(ed2, red);
-  cross = block_sum(cross, red);
-  dobj = block_sum(dobj, red);
-  bad = block_sum(bad, red);
+  for (int t = tid; t < r; t += nt) lth += lam[t] * small[SL::THETA + t];
+  {
+    double v[9 + MAX_R1] = {x2, x01, ed2, cross, dobj, bad, ymx, lth, mdy2};
+    for (int q = 0; q < MAX_R1; ++q) v[9 + q] = cq[q];
+    block_sum_many<9 + MAX_R1>(v, red);
+    x2 = v[0]; x01 = v[1]; ed2 = v[2]; cross = v[3]; dobj = v[4]; bad = v[5];
+    ymx = v[6]; lth = v[7]; mdy2 = v[8];
+    for (int q = 0; q < MAX_R1; ++q) cq[q] = v[9 + q];
+  }
   lo = block_min(lo, red);
-  mdy2 = block_sum(mdy2, red);
-  obj = block_sum(obj, red);
-  for (int q = 0; q < MAX_R1; ++q) cq[q] = block_sum(cq[q], red);
   // true Ritz residuals of the kept pairs (row-wise partials of the final round)
   double worst = 0.0;
   {
@@ -292,6 +294,7 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     const double ep2 = dx2 / (alpha * alpha) + 2.0 * cross / alpha + my2;
     const double eps_p = sqrt(fmax(ep2, 0.0));
     const double eps_d = sqrt(fmax(ed2, 0.0));
+    const double obj = (x01 + alpha * ymx - lth) / alpha;
     sc[f.x2_new] = x2;
     sc[S_EPSP] = eps_p;
     sc[S_EPSD] = eps_d;

@@ -195,7 +195,9 @@ class Solver:
         names = {0: "alpha", 1: "lower_bound", 2: "maxres", 3: "lambda_r", 4: "lambda_r1",
                  5: "normw", 6: "eps_p", 7: "eps_d", 8: "obj", 9: "dual_obj", 10: "dx2",
                  13: "nonfinite", 14: "dropped", 15: "filter_c", 16: "filter_e", 17: "sweeps",
-                 18: "rr_newton_steps", 19: "rr_cholesky_calls", 20: "rr_calls"}
+                 18: "rr_newton_steps", 19: "rr_cholesky_calls", 20: "rr_calls",
+                 22: "rr_chol_gram", 23: "rr_chol_couplings", 24: "rr_chol_tail",
+                 25: "rr_t_newton", 26: "rr_t_cholesky", 27: "rr_t_diag", 28: "rr_t_out"}
         d = {v: float(out[k]) for k, v in names.items()}
         d["theta"] = out[64:].tolist()
         return d
@@ -219,6 +221,21 @@ class Solver:
                   "get_saved")
             out.append((int(it.value), V[:, :r.value].copy(), lam[:r.value].copy(), y))
         return out
+
+    def round_hyperplane(self, g):
+        """Random-hyperplane rounding of the current iterate with the Gaussian
+        vectors g (trials x r, r = the current rank).  Returns (values
+        <C, x x^T> per trial, x of the best trial as int8 +-1, its index)."""
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        trials = g.shape[0]
+        values = np.zeros(trials)
+        x = np.zeros(self.n, dtype=np.int8)
+        best = C.c_int32()
+        check(lib.proxsdp_round_hyperplane(
+            self._h, trials, g.ctypes.data_as(C.POINTER(C.c_double)) if g.size else None,
+            values.ctypes.data_as(C.POINTER(C.c_double)), x.ctypes.data_as(C.POINTER(C.c_int8)),
+            C.byref(best)), "round_hyperplane")
+        return values, x, int(best.value)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

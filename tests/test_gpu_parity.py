@@ -7,10 +7,18 @@ Tolerances:
   Ritz residual of 1e-12 (spectra with a gap of at least 10% of ||S||).
 * iterates after K PDHG steps with converged eigensolves: max abs
   difference <= 1e-7 (relative to max |X|).
-* solves to rho <= 1e-4: objective within 1e-5 relative of the oracle's
-  objective at the same tolerance, and the oracle's certificate of the GPU
-  answer (one exact PDHG step from it) below 2e-4.
+* solves to rho <= 1e-4: the oracle's certificate of the GPU answer (one
+  exact PDHG step from it) below 2e-4, and the objective against the oracle's
+  objective at the same tolerance within OBJ_TOL: 1e-5 relative for max-cut
+  and 5e-4 for equipartition.  Equipartition has no strictly feasible primal
+  point (X 1 = 0 is forced), so a residual of 1e-4 fixes its objective only
+  loosely: the oracle's own answers at tol 1e-4 under different control
+  settings (check_every 5 / 10, window 30 / 50 / 100) spread by 2.8e-4
+  relative on G(50, 0.1) and 6.2e-5 on G(120, 0.05); for max-cut the same
+  spread is 1.6e-6 (G(150, 0.05)) and 2.7e-6 (G(400, 0.05)).
 """
+import json
+import os
 import math
 import sys
 
@@ -21,6 +29,21 @@ import instances as I
 import oracle as O
 
 pytestmark = pytest.mark.gpu
+
+OBJ_TOL = {"maxcut": 1e-5, "equip": 5e-4}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_refs.json")
+
+
+def _oracle_obj(kind, n, p, seed, tol=1e-4):
+    """The oracle's objective at `tol`: stored by tests/golden/make_oracle_refs.py
+    (which calls only the oracle) for the larger instances, solved here otherwise."""
+    key = f"{kind}_n{n}_p{p}_s{seed}_tol{tol:g}"
+    if os.path.exists(GOLDEN):
+        refs = json.load(open(GOLDEN))
+        if key in refs:
+            return refs[key]["obj"]
+    prob = I.maxcut(n, p, seed) if kind == "maxcut" else I.equipartition(n, p, seed)
+    return O.solve(prob, tol=tol).obj
 
 
 @pytest.fixture(scope="module")
@@ -229,16 +252,9 @@ def test_solve_matches_oracle(torch_cuda, kind, n, seed, full):
     _say("  cert", cert.rho_p, cert.rho_d, cert.rel_gap)
     assert max(cert.rho_p, cert.rho_d) <= 2e-4
     assert cert.lambda_min_X >= -1e-9 * max(1.0, np.abs(X).max())
-    if kind == "maxcut":
-        assert info["obj"] == pytest.approx(ref.obj, rel=1e-5)
-    else:
-        # equipartition has no strictly feasible primal point (X 1 = 0 is forced),
-        # so a residual of 1e-4 fixes the objective only up to the primal-dual gap;
-        # both answers must lie within the gap band of the oracle's certificate.
-        ref_cert = O.certificate(prob, ref.X, ref.y)
-        band = max(1e-5, 2.0 * max(ref_cert.rel_gap, cert.rel_gap))
-        _say("  equip band", band, "rel diff", abs(info["obj"] - ref.obj) / abs(ref.obj))
-        assert abs(info["obj"] - ref.obj) <= band * abs(ref.obj)
+    rel = abs(info["obj"] - ref.obj) / abs(ref.obj)
+    _say("  obj rel diff vs oracle", rel, "bound", OBJ_TOL[kind])
+    assert rel <= OBJ_TOL[kind]
     s.close()
 
 
@@ -302,31 +318,100 @@ def test_precision_form_strict_iterates_match_oracle(torch_cuda, kind, n, r, K, 
                                               ("equip", 300, 6, 2)])
 def test_precision_form_solve(torch_cuda, kind, n, seed, prec):
     """FP32 / BF16 precision form to 1e-4: the oracle's certificate of the
-    answer and the objective against the plain FP64 GPU form (stated error)."""
+    answer, and its objective against the oracle's (stated error, OBJ_TOL)."""
     from paper_1810_05231_amd import Solver
     _say("precision solve", kind, n, seed, "prec", prec)
     prob = I.maxcut(n, 0.05, seed) if kind == "maxcut" else I.equipartition(n, 0.05, seed)
-    s64 = Solver(prob, tol=1e-4)
-    i64 = s64.solve()
     s32 = Solver(prob, tol=1e-4, precision=prec)
     i32 = s32.solve()
-    _say("  fp64", i64["status_name"], i64["iters"], i64["r"], repr(i64["obj"]))
-    _say("  fp32", i32["status_name"], i32["iters"], i32["r"], repr(i32["obj"]))
+    _say("  gpu", i32["status_name"], i32["iters"], i32["r"], repr(i32["obj"]))
     assert i32["status_name"] == "converged"
     X, y = s32.solution(on_device=False)
     cert = O.certificate(prob, X, y)
-    rel = abs(i32["obj"] - i64["obj"]) / abs(i64["obj"])
-    _say("  cert", cert.rho_p, cert.rho_d, cert.rel_gap, "obj rel diff vs fp64", rel)
+    ref = _oracle_obj(kind, n, 0.05, seed)
+    rel = abs(i32["obj"] - ref) / abs(ref)
+    _say("  cert", cert.rho_p, cert.rho_d, cert.rel_gap, "obj rel diff vs oracle", rel)
     assert max(cert.rho_p, cert.rho_d) <= 2e-4
     assert cert.lambda_min_X >= -1e-9 * max(1.0, np.abs(X).max())
-    if kind == "maxcut":
-        assert rel <= 1e-4
-    else:
-        X64, y64 = s64.solution(on_device=False)
-        c64 = O.certificate(prob, X64, y64)
-        assert rel <= max(1e-4, 2.0 * max(cert.rel_gap, c64.rel_gap))
-    s64.close()
+    assert rel <= OBJ_TOL[kind]
     s32.close()
+
+
+# ------------------------------------------------- implicit operator form
+IMPLICIT = 3
+
+
+@pytest.mark.parametrize("kind,n,r,K", [("maxcut", 200, 4, 20), ("equip", 180, 3, 20),
+                                        ("snl", 302, 8, 20), ("planted", 300, 48, 10)])
+def test_implicit_form_iterates_match_oracle(torch_cuda, kind, n, r, K):
+    """No dense iterate: every pass applies W = V Lambda V^T + D + rank-one terms
+    in FP64; with converged eigensolves the iterates are the oracle's."""
+    from paper_1810_05231_amd import Solver
+    _say("implicit iterates", kind, n, r, K)
+    prob = _instance(kind, n)
+    alpha = 0.95 / O.Operators(prob).norm()
+    s = Solver(prob, r0=r, alpha=alpha, check_every=5, window=1000, eig_strict=1,
+               eig_tol=1e-13, max_iters=K, precision=IMPLICIT)
+    info = s.step(K)
+    Xg, yg = s.solution(on_device=False)
+    Xo, yo, out = _oracle_steps(prob, K, r, alpha)
+    scale = max(1.0, np.abs(Xo).max())
+    _say("  dX", np.abs(Xg - Xo).max() / scale, "dy", np.abs(yg - yo).max())
+    assert info["iters"] == K
+    assert np.abs(Xg - Xo).max() <= 1e-7 * scale
+    assert np.abs(yg - yo).max() <= 1e-7 * max(1.0, np.abs(yo).max())
+    assert info["eps_p"] == pytest.approx(out.eps_p, rel=1e-5, abs=1e-9)
+    assert info["eps_d"] == pytest.approx(out.eps_d, rel=1e-5, abs=1e-9)
+    s.close()
+
+
+@pytest.mark.parametrize("kind,n,seed", [("maxcut", 150, 3), ("equip", 120, 4)])
+def test_implicit_form_solve(torch_cuda, kind, n, seed):
+    """The implicit form to 1e-4: converged, certified by the oracle (one exact
+    step from the answer), objective as for the dense FP64 form."""
+    from paper_1810_05231_amd import Solver
+    _say("implicit solve", kind, n, seed)
+    prob = I.maxcut(n, 0.05, seed) if kind == "maxcut" else I.equipartition(n, 0.05, seed)
+    s = Solver(prob, tol=1e-4, precision=IMPLICIT)
+    info = s.solve()
+    _say("  gpu", info["status_name"], info["iters"], info["r"], repr(info["obj"]))
+    assert info["status_name"] == "converged"
+    X, y = s.solution(on_device=False)
+    cert = O.certificate(prob, X, y)
+    _say("  cert", cert.rho_p, cert.rho_d, cert.rel_gap)
+    assert max(cert.rho_p, cert.rho_d) <= 2e-4
+    ref = _oracle_obj(kind, n, 0.05, seed)
+    rel = abs(info["obj"] - ref) / abs(ref)
+    _say("  obj rel diff vs oracle", rel)
+    assert rel <= OBJ_TOL[kind]
+    s.close()
+
+
+# ------------------------------------------------- hyperplane rounding
+def test_hyperplane_rounding_matches_oracle(torch_cuda):
+    """Random-hyperplane rounding of the GPU's max-cut answer: the same factors
+    and Gaussian vectors through the oracle give the same signs (decided in
+    FP64 on both sides; entries whose sum is within rounding of zero are left
+    out of the comparison) and the same values <C, x x^T> = -cut."""
+    from paper_1810_05231_amd import Solver
+    prob = I.maxcut(300, 0.05, 3)
+    s = Solver(prob, tol=1e-4)
+    info = s.solve()
+    assert info["status_name"] == "converged"
+    V, lam, _ = s.get_state()
+    G = np.random.default_rng(11).standard_normal((64, lam.size))
+    vals, x, best = s.round_hyperplane(G)
+    C = O.dense_sym_from_coo(prob.n, prob.c_i, prob.c_j, prob.c_v)
+    xs, ovals = O.hyperplane_round(V, lam, C, G)
+    S = G @ (V * np.sqrt(lam)).T
+    tie = np.abs(S) <= 1e-12 * np.abs(S).max()
+    _say("rounding: best cut", -vals[best], "ties", int(tie.sum()), "sdp bound", -info["obj"])
+    assert not tie.any()
+    assert np.array_equal(vals, ovals)
+    assert best == int(np.argmin(ovals))
+    assert np.array_equal(x.astype(np.float64), xs[best])
+    assert -vals[best] <= -info["obj"] * (1 + 1e-4)
+    s.close()
 
 
 # ------------------------------------------------- sensor localisation
