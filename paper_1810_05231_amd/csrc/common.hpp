@@ -73,6 +73,7 @@ enum Scalar {
   S_RRT1,         //   Newton steps / Cholesky path / diagonalisation and sort /
   S_RRT2,         //   coefficients, residual estimates and next-basis matrices
   S_RRT3,
+  S_NPOS,         // leading positive Ritz values among the kept ones (last Rayleigh-Ritz)
   S_COUNT
 };
 
@@ -80,6 +81,7 @@ enum Scalar {
 struct IterRecord {
   double eps_p, eps_d, obj, dual_obj;
   double lambda_r, lambda_r1, maxres, normw;   // maxres relative to normw = max |theta|
+  double npos;                                 // positive kept Ritz values
 };
 
 // Device views of the preprocessed problem.

@@ -488,6 +488,7 @@ struct proxsdp_handle {
   double eps_lambda = 0;
   double rank_value = std::nan("");   // last confirmed rank-test value (upper estimate)
   int verify_steps = 0;               // exact-step convergence checks taken
+  int width_changes = 0;
   double verify_q = 1.0;              // last failed check: exact / reported residual
   double strict_tol = 0.0;            // eigensolve target of the strict rounds (0: eig_tol)
   double eig_rel_user = 0.2;          // eig_rel as created (the checks may lower it)
@@ -539,10 +540,15 @@ static void prof_mark(proxsdp_handle* H, std::vector<hipEvent_t>& pool, int& cnt
   (void)hipEventRecord(pool[idx], H->st);
   if (start) {
     if (&pool == &H->ev_pass) H->prof_k.push_back(H->k);
-    else H->prof_r.push_back(H->r);
+    else H->prof_r.push_back(H->full ? H->r : std::min(H->r, H->k));
   }
   if (!start) ++cnt;
 }
+
+// Number of Ritz pairs kept as factors: the target rank r of Algorithm 2
+// within the subspace width k (k >= r whenever the width is automatic; a
+// fixed `block` caps r at k).
+static int rf(const proxsdp_handle* H) { return H->full ? H->r : std::min(H->r, H->k); }
 
 static size_t carve(proxsdp_handle* H, void* ws) {
   const int npad = H->npad;
@@ -907,11 +913,11 @@ static void eig_round(proxsdp_handle* H, int par, bool final_round) {
   } else {
     launch_implicit(H, Bc, H->Z);
   }
-  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, jacobi_tol(H), st);
+  launch_rr(H->gram_part, H->nsl, H->small, H->k, rf(H), lam_slot(par), 1, jacobi_tol(H), st);
   if (final_round)
-    launch_rowwise(H, Bc, H->V[par], H->r, H->V[1 - par], H->r_old, Bn, st);
+    launch_rowwise(H, Bc, H->V[par], rf(H), H->V[1 - par], H->r_old, Bn, st);
   else
-    launch_rowwise(H, Bc, nullptr, H->r, nullptr, 0, Bn, st);
+    launch_rowwise(H, Bc, nullptr, rf(H), nullptr, 0, Bn, st);
   H->bcur = nb;
   H->passes += 1;
 }
@@ -960,8 +966,8 @@ static void eig_iteration(proxsdp_handle* H, int par, int m) {
     // precision form: the Rayleigh-Ritz pass applies W exactly (FP64 refinement)
     launch_implicit(H, H->B[cur], H->Z);
   }
-  launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(par), 1, jacobi_tol(H), st);
-  launch_rowwise(H, H->B[cur], H->V[par], H->r, H->V[1 - par], H->r_old, H->B[nb], st);
+  launch_rr(H->gram_part, H->nsl, H->small, H->k, rf(H), lam_slot(par), 1, jacobi_tol(H), st);
+  launch_rowwise(H, H->B[cur], H->V[par], rf(H), H->V[1 - par], H->r_old, H->B[nb], st);
   H->bcur = nb;
   H->passes += 1;
 }
@@ -973,7 +979,7 @@ static void pattern_and_write(proxsdp_handle* H, int par, int ring_slot) {
   FinArgs f{};
   f.fac_part = H->fac_part;
   f.nslices = H->full ? 1 : H->nsl;
-  f.r = H->r;
+  f.r = rf(H);
   f.r_old = H->r_old;
   f.lam_new = lam_slot(par);
   f.lam_old = lam_slot(1 - par);
@@ -987,12 +993,12 @@ static void pattern_and_write(proxsdp_handle* H, int par, int ring_slot) {
   f.ring_slot = ring_slot;
   if (H->prec == PROXSDP_FP64) {
     prof_mark(H, H->ev_write, H->n_write, true);
-    launch_write(H, H->W, H->prec, H->npad, H->V[par], H->r, lam_slot(par), true, true, &f);
+    launch_write(H, H->W, H->prec, H->npad, H->V[par], rf(H), lam_slot(par), true, true, &f);
     prof_mark(H, H->ev_write, H->n_write, false);
   } else {
     // precision form: finalise only; the low-precision W is written when a
     // dense filter pass needs it
-    launch_write(H, H->Wl, H->prec, H->npad, H->V[par], H->r, lam_slot(par), true, true, &f, false);
+    launch_write(H, H->Wl, H->prec, H->npad, H->V[par], rf(H), lam_slot(par), true, true, &f, false);
     H->w_fresh = false;
   }
 }
@@ -1011,7 +1017,7 @@ static void iterate_once(proxsdp_handle* H) {
     for (int rd = 0; rd < 200; ++rd) {
       eig_round(H, par, false);
       double mr = 1.0;
-      if (true_maxres(H, H->r, &mr)) break;
+      if (true_maxres(H, rf(H), &mr)) break;
       if (mr <= target) break;
     }
     eig_round(H, par, true);
@@ -1028,11 +1034,11 @@ static void iterate_once(proxsdp_handle* H) {
   }
   // dual step
   hipLaunchKernelGGL(k_gather_dual, dim3(H->nrow_blocks), dim3(ROW_LANES * ROWS_PER_BLOCK), 0, st, H->dp, H->V[par],
-                     H->r, H->small, lam_slot(par), H->fac_part, H->full ? 1 : H->nsl, H->r_old,
+                     rf(H), H->small, lam_slot(par), H->fac_part, H->full ? 1 : H->nsl, H->r_old,
                      H->y, H->y_old, H->MX, H->MX_old, H->row_part);
   // next W, residuals
   pattern_and_write(H, par, -1);   // ring slot from the device iteration counter
-  H->r_old = H->r;
+  H->r_old = rf(H);
   H->iters += 1;
 }
 
@@ -1088,8 +1094,23 @@ static int run_round(proxsdp_handle* H, int count) {
   H->passes += it->second.d_passes;
   H->bcur = it->second.end_bcur;
   H->w_fresh = it->second.end_wfresh;
-  H->r_old = H->r;
+  H->r_old = rf(H);
   return PROXSDP_OK;
+}
+
+// Re-layout of the basis block with a new subspace width: the leading
+// columns (the Ritz directions of the largest values) are kept, new ones are
+// random.
+static void set_width(proxsdp_handle* H, int k_new) {
+  if (k_new == H->k) return;
+  const int64_t cnt = (int64_t)H->npad * k_new;
+  const int nb = (H->bcur + 1) % 3;
+  H->width_changes += 1;
+  hipLaunchKernelGGL(k_fill_basis, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, H->st,
+                     H->B[nb], k_new, H->B[H->bcur], H->k, std::min(H->k, k_new), H->n,
+                     H->npad, (uint32_t)(H->opt.seed * 7919 + H->rank_updates + 131 * H->width_changes));
+  H->bcur = nb;
+  H->k = k_new;
 }
 
 static void set_rank(proxsdp_handle* H, int r_new, int why) {
@@ -1100,17 +1121,7 @@ static void set_rank(proxsdp_handle* H, int r_new, int why) {
   H->path_r.push_back(r_new);
   H->path_why.push_back(why);
   if (H->full) return;
-  const int k_new = H->opt.block ? H->opt.block : k_for_r(r_new);
-  if (k_new != H->k) {
-    // re-layout the basis with the new width: old columns kept, new ones random
-    const int64_t cnt = (int64_t)H->npad * k_new;
-    const int nb = (H->bcur + 1) % 3;
-    hipLaunchKernelGGL(k_fill_basis, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, H->st,
-                       H->B[nb], k_new, H->B[H->bcur], H->k, std::min(H->k, k_new), H->n,
-                       H->npad, (uint32_t)(H->opt.seed * 7919 + H->rank_updates));
-    H->bcur = nb;
-    H->k = k_new;
-  }
+  set_width(H, H->opt.block ? H->opt.block : k_for_r(r_new));
 }
 
 static int read_records(proxsdp_handle* H, int first_iter, int count, std::vector<IterRecord>& out) {
@@ -1171,13 +1182,13 @@ static int rank_probe(proxsdp_handle* H, double thr, int* verdict, double* ub_ou
   hipStream_t st = H->st;
   const int slot = H->iters & 1;   // lambda slot the next iteration overwrites
   const bool plus1 = H->opt.rank_test == PROXSDP_RANK_TEST_LAMBDA_R_PLUS_1;
-  const int idx = plus1 ? H->r : H->r - 1;   // 0-based index of the tested value
-  if (idx >= H->k) {
-    // no such Ritz value in the subspace (the caps keep r + 1 <= k for this test)
-    *verdict = RANK_UNDECIDED;
-    *ub_out = std::nan("");
-    return PROXSDP_OK;
-  }
+  const int want = plus1 ? H->r : H->r - 1;   // 0-based index Algorithm 2's test reads
+  // A block narrower than that index tests its last value instead:
+  // lambda_want <= lambda_idx, so an upper estimate of lambda_idx below the
+  // threshold passes the test, but a large theta_idx says nothing about
+  // lambda_want.
+  const int idx = std::min(want, H->k - 1);
+  const bool exact_index = idx == want;
   const int ncol = idx + 1;
   const int per_batch = 8, batches = 4;
   *verdict = RANK_UNDECIDED;
@@ -1192,11 +1203,11 @@ static int rank_probe(proxsdp_handle* H, double thr, int* verdict, double* ub_ou
       } else {
         launch_implicit(H, Bc, H->Z);
       }
-      launch_rr(H->gram_part, H->nsl, H->small, H->k, H->r, lam_slot(slot), 1, 1e-15, st,
+      launch_rr(H->gram_part, H->nsl, H->small, H->k, rf(H), lam_slot(slot), 1, 1e-15, st,
                 last ? 0 : 10);
       const int nb = (H->bcur + 1) % 3;
       // the last round of a batch also forms the true residuals of columns < ncol
-      launch_rowwise(H, Bc, nullptr, last ? ncol : H->r, nullptr, 0, H->B[nb], st);
+      launch_rowwise(H, Bc, nullptr, last ? ncol : rf(H), nullptr, 0, H->B[nb], st);
       H->bcur = nb;
       H->passes += 1;
     }
@@ -1209,8 +1220,11 @@ static int rank_probe(proxsdp_handle* H, double thr, int* verdict, double* ub_ou
     const double ub = th + rel * std::max(scale, 1e-300);
     *ub_out = ub;
     if (!std::isfinite(ub)) break;
-    if (std::max(th, 0.0) > thr) *verdict = RANK_FAIL;
-    else if (std::max(ub, 0.0) <= thr) *verdict = RANK_PASS;
+    if (std::max(ub, 0.0) <= thr) *verdict = RANK_PASS;
+    else if (std::max(th, 0.0) > thr) {
+      if (exact_index) *verdict = RANK_FAIL;
+      else break;   // more positive values than the block holds: undecided
+    }
   }
   return PROXSDP_OK;
 }
@@ -1311,7 +1325,7 @@ static int control(proxsdp_handle* H) {
       if (H->full) {
         const double lam_t = plus1 ? rec.lambda_r1 : rec.lambda_r;   // exact eigenvalues
         verdict = std::max(lam_t, 0.0) <= thr ? RANK_PASS : RANK_FAIL;
-      } else if (!plus1 && std::max(rec.lambda_r, 0.0) > thr) {
+      } else if (!plus1 && rf(H) == H->r && std::max(rec.lambda_r, 0.0) > thr) {
         // a positive r-th Ritz value is kept, hence resolved, and bounds
         // lambda_r from below: the test fails without confirmation
         verdict = RANK_FAIL;
@@ -1399,7 +1413,7 @@ static int warm_start(proxsdp_handle* H, const double* src = nullptr, int nsrc =
     eig_round(H, 0, false);
     if (rd % 4 == 3) {
       double mr = 1;
-      const int rc = true_maxres(H, H->r, &mr);
+      const int rc = true_maxres(H, rf(H), &mr);
       if (rc) return rc;
       if (mr <= 1e-3) break;
     }
@@ -1446,6 +1460,7 @@ static int reset_buffers(proxsdp_handle* H) {
   H->saved.clear();
   H->rank_value = std::nan("");
   H->verify_steps = 0;
+  H->width_changes = 0;
   H->verify_q = 1.0;
   H->strict_tol = 0.0;
   H->opt.eig_rel = H->eig_rel_user;
@@ -1813,11 +1828,11 @@ int proxsdp_set_state(proxsdp_handle* H, int32_t r, const double* V, const doubl
   // W0 = X0 - alpha (C - M*(y0)) from the factors (its record is not used);
   // the finalisation it runs overwrites ||X||^2 of parity 1, set afterwards
   H->r_old = r;
-  const int r_work = H->r;
+  const int r_work = H->opt.full_eig ? n : std::max(H->r, std::min(std::max(r, 1), H->r_cap));
+  H->k = H->full ? 16 : (H->opt.block ? H->opt.block : k_for_r(r_work));   // k >= r
   H->r = r;
   pattern_and_write(H, 1, RING - 1);
-  H->r = H->opt.full_eig ? n : std::max(r_work, std::min(std::max(r, 1), H->r_cap));
-  H->k = H->full ? 16 : (H->opt.block ? H->opt.block : k_for_r(H->r));
+  H->r = r_work;
   HIP_OK(hipMemcpyAsync(H->small + SL::SC + S_X2 + 1, &sc2[0], sizeof(double), hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(H->small + SL::SC + S_NONFINITE, &sc2[1], sizeof(double), hipMemcpyHostToDevice, st));
   // Ritz basis: the given factors first

@@ -978,6 +978,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
       sc[S_LAMR] = vals[rk - 1];
       sc[S_LAMR1] = (rk < k) ? vals[rk] : __builtin_nan("");
       sc[S_NORMW] = scale;
+      sc[S_NPOS] = (double)npos;
       sc[S_CHOLFIX] = (double)flag[0];
       sc[S_FILTC] = fc;
       sc[S_FILTE] = fe;

@@ -313,6 +313,7 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     rec.lambda_r1 = sc[S_LAMR1];
     rec.maxres = sc[S_MAXRES];
     rec.normw = sc[S_NORMW];
+    rec.npos = sc[S_NPOS];
     // ring slot: given (set-up record) or the device iteration counter, so
     // that a captured round of iterations can be replayed
     int slot = f.ring_slot;
