@@ -47,7 +47,7 @@ def main():
     # the serving stream runs one HIP stream per in-flight solve; more hardware
     # queues than HIP's default of 4 let more of them run concurrently (set
     # before HIP initialises; measured 1.2 -> 1.6 solves/s on 32 requests)
-    if "--serving" in sys.argv or "--serving-only" in sys.argv:
+    if "--no-serving" not in sys.argv:
         slots = 16
         if "--slots" in sys.argv:
             slots = int(sys.argv[sys.argv.index("--slots") + 1])
@@ -70,17 +70,21 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16", "implicit"], default="fp64",
                     help="storage of W for the timed steps (fp32 / bf16 = precision form, "
                          "implicit = no dense W)")
-    ap.add_argument("--workload", choices=["maxcut", "equip", "snl"], default="maxcut",
+    ap.add_argument("--workload", choices=["maxcut", "equip", "snl", "mimo"], default="maxcut",
                     help="maxcut / equip: G(n, p); snl: --n sensors (2000 for the full case)")
     ap.add_argument("--progress", type=int, default=0,
                     help="solve in chunks of this many iterations with a progress line each")
     ap.add_argument("--time-limit", type=float, default=0.0, help="solver time limit (s)")
     ap.add_argument("--snl-noise", type=float, default=0.0,
                     help="snl: multiplicative distance noise (0 = exact distances, as in Section 5.2)")
-    ap.add_argument("--serving", type=int, default=0,
-                    help="also run the serving stream with this many requests (0 = skip)")
+    ap.add_argument("--serving", type=int, default=64,
+                    help="also run this many requests of the serving stream (the stream's first "
+                         "requests; 512 is the whole stream)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serving-precision", choices=["fp32", "implicit"], default="fp32",
+                    help="form of the served solves")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
-    ap.add_argument("--serving-sat", type=int, default=0,
+    ap.add_argument("--serving-sat", type=int, default=32,
                     help="serving: requests of the saturation run that sets the arrival rate "
                          "(default: all of them)")
     ap.add_argument("--slots", type=int, default=16, help="serving: solves in flight")
@@ -114,6 +118,8 @@ def main():
         prob = I.maxcut(n, args.p, args.seed)
     elif args.workload == "equip":
         prob = I.equipartition(n, args.p, args.seed)
+    elif args.workload == "mimo":
+        prob = I.mimo(n, args.seed)
     else:
         prob = I.snl(n, args.seed, noise=args.snl_noise)
     log(f"instance {prob.name}: n={prob.n} m={prob.m} p={prob.p} ({time.perf_counter()-t0:.1f}s)")
@@ -253,13 +259,21 @@ def main():
         "frac_hbm": round((pass_bytes + write_bytes) / max(sweep_s, 1e-12) / 1e9 / PEAK_HBM_GBS, 4),
         "unique_entry_GBps": round(uniq / max(sweep_s, 1e-12) / 1e9, 1),
     }
-    serving = serving_bench(args, dev) if args.serving else None
+    serving = serving_bench(args, dev) if (args.serving and not args.no_serving and not args.iters) else None
     full_cmp = None
     if args.workload != "snl" and n <= 4000 and not args.iters:
         full_cmp = full_projection_cost(s, dev, sum(times) / len(times), last)
     answers = {}
     if not args.iters:
         answers[args.precision] = s.solution(on_device=False)
+    mimo_check = None
+    if args.workload == "mimo" and not args.iters:
+        X_ans = answers[args.precision][0]
+        xhat = np.sign(X_ans[:n, n])
+        errs = int(np.sum(xhat != prob.meta["x_true"]))
+        mimo_check = {"bit_errors": errs, "recovered_signal": errs == 0,
+                      "signal": "sign of the last column of X against the transmitted x"}
+        log(f"mimo: {errs} bit errors")
     prec = None
     if not args.no_precision_form and not args.iters and args.precision == "fp64":
         prec = {}
@@ -288,8 +302,10 @@ def main():
                   "bf16": "bf16 W / f64 Rayleigh-Ritz"}[args.precision],
         "data": "synthetic (seeded; Erdos-Renyi graphs with unit weights, or random sensor networks)",
         "config": {
-            "workload": (f"{args.workload} G({n},{args.p}) seed {args.seed}" if args.workload != "snl"
-                         else f"sensor localisation, {n} sensors, seed {args.seed}, noise {args.snl_noise}")
+            "workload": ({"snl": f"sensor localisation, {n} sensors, seed {args.seed}, noise {args.snl_noise}",
+                          "mimo": f"binary MIMO detection, n = {n} (X in S^{n + 1}), seed {args.seed}, "
+                                  f"noise sigma 0.1"}.get(args.workload,
+                                                          f"{args.workload} G({n},{args.p}) seed {args.seed}"))
                         + f", {args.precision.upper()} LR-PD-SDP to {args.tol:g}",
             "n": int(prob.n), "m": int(prob.m), "p": int(prob.p), "tol": args.tol,
             "iters": last["iters"], "final_rank": last["r"], "passes": last["passes"],
@@ -301,12 +317,14 @@ def main():
                                     "couplings": int(dbg["rr_chol_couplings"]),
                                     "tail_bound": int(dbg["rr_chol_tail"])},
             "verify_steps": last["verify_steps"],
+            "rr_newton_steps_per_call": round(dbg["rr_newton_steps_total"] / max(dbg["rr_calls"], 1), 2),
             "rr_phase_s": {"newton": round(dbg["rr_t_newton"], 4), "cholesky": round(dbg["rr_t_cholesky"], 4),
                            "diagonalise": round(dbg["rr_t_diag"], 4), "output": round(dbg["rr_t_out"], 4)},
         },
         "roofline": roofline,
         "precision_form": prec,
         "oracle_check": check_block,
+        "mimo_detection": mimo_check,
         "full_eig_comparison": full_cmp,
         "serving": serving,
         "cpu_baseline": cpu,
@@ -322,13 +340,14 @@ def serving_bench(args, dev):
     import instances as I
     from paper_1810_05231_amd.serving import Request, Server, percentile
     N = args.serving or 512
-    opts = dict(precision=1, tol=args.tol, graphs=1)
+    code = {"fp32": 1, "implicit": 3}[args.serving_precision]
+    opts = dict(precision=code, tol=args.tol, graphs=1)
     srv = Server(device=dev, budget_bytes=int(args.budget_gib * (1 << 30)), max_slots=args.slots,
                  **opts)
     Ns = min(N, args.serving_sat) if args.serving_sat > 0 else N
     base = I.serving_stream(N, seed=args.seed, rate=None)[:Ns]
     log(f"serving: {N} requests ({Ns} in the saturation run), n in [100, 2000], G(n, 8/n), "
-        f"FP32 form, {args.slots} slots")
+        f"{args.serving_precision} form, {args.slots} slots")
     def progress(r, _s):
         if r.rid % 16 == 0:
             log(f"  done rid {r.rid} n={r.n} {r.status} iters={r.iters} latency={r.latency:.3f}s")
@@ -347,8 +366,10 @@ def serving_bench(args, dev):
     lat = [r.latency for r in res2]
     ok2 = sum(r.status == "converged" for r in res2)
     out = {
-        "workload": f"{N} requests, max-cut/equipartition (fair coin), n ~ U[100, 2000], "
-                    f"G(n, 8/n), FP32 precision form, Poisson arrivals",
+        "workload": (f"first {N} of the 512-request stream" if N < 512 else "512 requests")
+                    + ", max-cut/equipartition (fair coin), n ~ U[100, 2000], G(n, 8/n), "
+                    + {"fp32": "FP32 precision form", "implicit": "implicit FP64 form"}[args.serving_precision]
+                    + ", Poisson arrivals",
         "slots": args.slots, "budget_GiB": args.budget_gib,
         "saturated_solves_per_s": round(thr, 3), "saturated_makespan_s": round(makespan, 3),
         "saturation_requests": Ns, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),

@@ -63,12 +63,14 @@ extern "C" {
 #define PROXSDP_STATUS_MAX_ITERS 2
 #define PROXSDP_STATUS_TIME_LIMIT 3
 #define PROXSDP_STATUS_NUMERICAL 4     /* NaN/Inf in the iterate             */
-/* The residual test passed but Algorithm 2's rank test could not be decided:
- * after the confirmation rounds of the partial eigensolve the Ritz value
- * tested lies below the rank-test threshold while its upper estimate (Ritz
- * value plus the norm of its Ritz residual) lies above it, and r is at its
- * cap, so the r <- 2r step that the undecided test calls for cannot be taken.
- * The iterate is returned as it is; it is not certified optimal. */
+/* The residual test passed but convergence could not be decided: either
+ * Algorithm 2's rank test stayed undecided at the rank cap (after the
+ * confirmation rounds of the partial eigensolve the tested Ritz value lies
+ * below the rank-test threshold while its upper estimate, Ritz value plus
+ * the norm of its Ritz residual, lies above it, and the r <- 2r step that an
+ * undecided test calls for cannot be taken), or the exact-step check could
+ * not converge its eigensolve within 1000 rounds three times.  The iterate is returned
+ * as it is; it is not certified optimal. */
 #define PROXSDP_STATUS_EIG_NOT_CONVERGED 5
 /* The residual test passed, the rank test failed and r is at its cap
  * (r_max < n, or the automatic cap of the partial path), so Algorithm 2's
@@ -199,10 +201,15 @@ typedef struct {
   int32_t verify_steps; /* exact-step convergence checks taken: once the residual
                            and rank tests pass on the partial path with the
                            adaptive eigensolve accuracy, one more iteration runs
-                           with the kept Ritz pairs converged (absolute Ritz
-                           residual <= max(eig_tol max|theta|, 0.01 alpha eps_p)),
-                           and the solve stops only if that exact step's
-                           residuals meet tol.  Otherwise the iteration
+                           with eigensolver rounds until the error bound of its
+                           projection, sqrt(sum over the kept pairs of
+                           min(||W v - theta v||, theta)^2), is below
+                           0.1 alpha tol min(1 + ||C||_F, (1 + ||[b; h]||) / 0.95),
+                           a tenth of what the stopping rule allows either
+                           residual (at most 1000 rounds; after three
+                           checks that cannot get there the solve stops with
+                           EIG_NOT_CONVERGED), and the solve stops only if that
+                           exact step's residuals meet tol.  Otherwise the iteration
                            continues: with the exact residual q times the
                            reported one, the next check waits for reported
                            residuals below tol / (1.02 q), and eig_rel is
@@ -365,7 +372,9 @@ int proxsdp_rank_path(proxsdp_handle *h, int32_t *iters, int32_t *ranks, int32_t
  * non-orthonormal / couplings among the kept pairs stayed above 1e-4 max|theta|
  * / the bound on the unresolved tail exceeded the r-th value, 25 .. 28 seconds
  * the Rayleigh-Ritz steps spent in their Newton refinement / Cholesky path /
- * diagonalisation / coefficient output, from the device clock) followed by the Ritz values of the last
+ * diagonalisation / coefficient output, from the device clock, 29 positive
+ * kept Ritz values, 30 the top Ritz value in the filter's variable, 31 Newton
+ * refinement steps of all Rayleigh-Ritz calls) followed by the Ritz values of the last
  * Rayleigh-Ritz step in out[64 ..] if count > 64.  Synchronises. */
 int proxsdp_debug_scalars(proxsdp_handle *h, double *out, int32_t count);
 

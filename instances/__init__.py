@@ -23,6 +23,8 @@ Workloads (recipes stated with each generator):
 * ``equipartition`` -- Section 5.1: min <L, X>, diag(X) = 1, <11^T, X> = 0.
 * ``snl``           -- Section 5.2: sensor network localisation with noisy
                        two-sided distance inequalities.
+* ``mimo``          -- Section 5.3: binary MIMO detection, dense cost and
+                       element-wise box inequalities.
 * ``random_symmetric`` -- dense symmetric test matrices with a prescribed
                        spectrum, for the PSD-projection entry point.
 """
@@ -45,6 +47,8 @@ __all__ = [
     "from_edges_maxcut",
     "from_edges_equipartition",
     "planted_lowrank",
+    "mimo",
+    "mimo_signal",
 ]
 
 
@@ -305,6 +309,56 @@ def snl(n_sensors: int, seed: int, radius: float = 0.3, noise: float = 0.05,
     if return_truth:
         return prob, pos, anchors
     return prob
+
+
+# ----------------------------------------------------------------------- MIMO
+def mimo_signal(n: int, seed: int, sigma: float = 0.1):
+    """Channel, signal and received vector of a binary MIMO instance
+    (Section 5.3): H is n x n with i.i.d. N(0, 1) entries, x in {-1, +1}^n
+    uniform, y = H x + sigma * eps with eps ~ N(0, I).  One PCG64 stream seeded
+    with ``seed``, drawn in the order H (row-major), x, eps."""
+    rng = np.random.default_rng(seed)
+    H = rng.standard_normal((n, n))
+    x = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    y = H @ x + sigma * rng.standard_normal(n)
+    return H, x, y
+
+
+def mimo(n: int, seed: int, sigma: float = 0.1) -> Problem:
+    """Binary MIMO detection relaxation (Section 5.3) on X in S^(n+1):
+
+        minimize tr(L X)  s.t.  X_ii = 1 (i = 0..n),  -1 <= X_ij <= 1 (i < j),  X PSD,
+
+    L = [[H^T H, -H^T y], [-y^T H, y^T y]], so that for x in {-1, +1}^n,
+    [x; 1]^T L [x; 1] = ||H x - y||^2.  C = L is dense (all (n+1)(n+2)/2
+    upper-triangle triplets).  Each off-diagonal pair (i, j), in row-major
+    order of the upper triangle, gives two inequality rows: X_ij <= 1 (row
+    n + 1 + 2q, triplet (i, j, 1/2)) and -X_ij <= 1 (row n + 2 + 2q, triplet
+    (i, j, -1/2)); the diagonal is fixed by the equalities, so its box rows
+    are left out.  At high signal-to-noise ratio the relaxation is exact: the
+    optimum is X = [x; 1][x; 1]^T with x the transmitted signal.
+    """
+    H, x, y = mimo_signal(n, seed, sigma)
+    N = n + 1
+    L = np.zeros((N, N))
+    L[:n, :n] = H.T @ H
+    L[:n, n] = -H.T @ y
+    L[n, :n] = L[:n, n]
+    L[n, n] = y @ y
+    iu, ju = np.triu_indices(N)
+    a_row0, a_i0, a_j0, a_v0 = _diag_rows(N)
+    ou, ov = np.triu_indices(N, 1)
+    q = np.arange(ou.size)
+    r_up = N + 2 * q
+    a_row = np.concatenate([a_row0, r_up, r_up + 1])
+    a_i = np.concatenate([a_i0, ou, ou])
+    a_j = np.concatenate([a_j0, ov, ov])
+    a_v = np.concatenate([a_v0, np.full(ou.size, 0.5), np.full(ou.size, -0.5)])
+    return Problem(n=N, m=N, p=2 * ou.size, c_i=iu, c_j=ju, c_v=L[iu, ju],
+                   a_row=a_row, a_i=a_i, a_j=a_j, a_v=a_v,
+                   b=np.ones(N), h=np.ones(2 * ou.size),
+                   name=f"mimo_n{n}_s{seed}",
+                   meta=dict(kind="mimo", n_signal=n, seed=seed, sigma=sigma, x_true=x))
 
 
 # ------------------------------------------------------ dense test matrices

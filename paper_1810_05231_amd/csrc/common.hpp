@@ -74,6 +74,8 @@ enum Scalar {
   S_RRT2,         //   coefficients, residual estimates and next-basis matrices
   S_RRT3,
   S_NPOS,         // leading positive Ritz values among the kept ones (last Rayleigh-Ritz)
+  S_FILTX1,       // (theta_1 - c) / e: the largest Ritz value in the filter's scaled variable
+  S_RRSTEPS,      // Newton refinement steps of all Rayleigh-Ritz calls since create/reset
   S_COUNT
 };
 
@@ -82,6 +84,7 @@ struct IterRecord {
   double eps_p, eps_d, obj, dual_obj;
   double lambda_r, lambda_r1, maxres, normw;   // maxres relative to normw = max |theta|
   double npos;                                 // positive kept Ritz values
+  double filt_x1;                              // (theta_1 - c) / e of the Chebyshev filter
 };
 
 // Device views of the preprocessed problem.
@@ -112,6 +115,7 @@ struct DevProblem {
   const double* r1_u;     // n_r1 x npad
   const int* row_r1;      // rows: rank-one term index or -1
   const double* rhs;      // [b; h] scaled
+  double norm_c;          // ||C||_F, an upper bound of lambda_max(C)
 };
 
 // Partial-buffer strides (doubles per slice / per block).
@@ -121,7 +125,7 @@ constexpr int VB_STRIDE = KMAX * KMAX + MAX_R1 * KMAX;  // per-slice partials of
 constexpr int ROW_PART = 5;                 // eps_d^2, <dMX, dy>, dual obj, nonfinite, <y, M(X+)>
 constexpr int ROW_LANES = 8;                // threads per constraint row in the dual step
 constexpr int ROWS_PER_BLOCK = 256 / ROW_LANES;
-constexpr int PAT_PART = 4 + MAX_R1;        // min gersh, ||M*dy||^2 (sparse), unused x2, cross_q
+constexpr int PAT_PART = 4 + MAX_R1;        // min gersh of D, ||M*dy||^2 (sparse), min gersh of M*(y), unused, cross_q
 
 // Number of SLICE-row workgroups covering npad rows.
 inline int n_slices(int npad) { return (npad + SLICE - 1) / SLICE; }

@@ -488,9 +488,13 @@ struct proxsdp_handle {
   double eps_lambda = 0;
   double rank_value = std::nan("");   // last confirmed rank-test value (upper estimate)
   int verify_steps = 0;               // exact-step convergence checks taken
+  int verify_unconverged = 0;         // of those, checks whose eigensolve missed its bound
   int width_changes = 0;
+  int cheb_max = 2;                   // largest pass count of one filtered Rayleigh-Ritz step
   double verify_q = 1.0;              // last failed check: exact / reported residual
-  double strict_tol = 0.0;            // eigensolve target of the strict rounds (0: eig_tol)
+  int strict_rounds = 200;            // round budget of the strict schedule
+  double strict_abs = 0.0;            // > 0: the strict rounds stop on the step error bound
+  bool strict_converged = false;      // the last strict eigensolve met its target
   double eig_rel_user = 0.2;          // eig_rel as created (the checks may lower it)
   // Algorithm 2's intermediate feasible solutions X_[r] (host copies)
   struct Saved {
@@ -661,6 +665,7 @@ static void fill_dev_problem(proxsdp_handle* H) {
   d.n_pat = (int)h.pat_a.size();
   d.tiles_side = h.npad / TILE;
   d.n_r1 = h.n_r1;
+  d.norm_c = h.norm_c;
   for (int q = 0; q < MAX_R1; ++q) {
     d.r1_row[q] = q < h.n_r1 ? h.r1_row[q] : 0;
     d.r1_sigma[q] = q < h.n_r1 ? h.r1_sigma[q] : 0.0;
@@ -885,6 +890,28 @@ static int true_maxres(proxsdp_handle* H, int r, double* out) {
   HIP_OK(hipStreamSynchronize(H->st));
   return PROXSDP_OK;
 }
+// Error bound of the step's projection from the last round's Ritz pairs:
+// with residuals rho_t = ||W v_t - theta_t v_t|| of the kept pairs, W differs
+// by about 2 ||R|| from a matrix whose eigenpairs they are, and the PSD
+// projection is 1-Lipschitz; a kept pair with theta_t < rho_t moves X by at most
+// about theta_t whatever its vector.  Returns sqrt(sum_t min(rho_t, theta_t)^2)
+// over the kept positive pairs (absolute units; synchronises).
+static int step_error(proxsdp_handle* H, int r, double* out) {
+  hipLaunchKernelGGL(k_reduce_res, dim3(1), dim3(256), 0, H->st, H->fac_part, H->nsl, r, H->small);
+  double th[KMAX], rel[KMAX], scale = 0;
+  HIP_OK(hipMemcpyAsync(th, H->small + SL::THETA, r * sizeof(double), hipMemcpyDeviceToHost, H->st));
+  HIP_OK(hipMemcpyAsync(rel, H->small + SL::RES, r * sizeof(double), hipMemcpyDeviceToHost, H->st));
+  HIP_OK(hipMemcpyAsync(&scale, H->small + SL::SC + S_NORMW, sizeof(double), hipMemcpyDeviceToHost, H->st));
+  HIP_OK(hipStreamSynchronize(H->st));
+  double e2 = 0;
+  for (int t = 0; t < r && th[t] > 0.0; ++t) {
+    const double e = std::min(rel[t] * scale, th[t]);
+    e2 += e * e;
+  }
+  *out = std::isfinite(e2) ? std::sqrt(e2) : INFINITY;
+  return PROXSDP_OK;
+}
+
 static int x2_slot(int parity) { return SL::SC + S_X2 + parity; }
 
 // Eigensolver rounds on the current W with the current basis.  `final_round`
@@ -927,7 +954,7 @@ static void eig_round(proxsdp_handle* H, int par, bool final_round) {
 // three-term recurrence, fused into the reduction of each pass; c, e from the
 // last Rayleigh-Ritz step) and one pass followed by Rayleigh-Ritz, the Ritz
 // factors V[par] and the next basis (degree-one filter of the Ritz vectors).
-static void eig_iteration(proxsdp_handle* H, int par, int m) {
+static void eig_iteration(proxsdp_handle* H, int par, int m, bool final_round = true) {
   hipStream_t st = H->st;
   const double* filt = H->small + SL::SC + S_FILTC;
   int prev = -1, cur = H->bcur;
@@ -967,7 +994,10 @@ static void eig_iteration(proxsdp_handle* H, int par, int m) {
     launch_implicit(H, H->B[cur], H->Z);
   }
   launch_rr(H->gram_part, H->nsl, H->small, H->k, rf(H), lam_slot(par), 1, jacobi_tol(H), st);
-  launch_rowwise(H, H->B[cur], H->V[par], rf(H), H->V[1 - par], H->r_old, H->B[nb], st);
+  if (final_round)
+    launch_rowwise(H, H->B[cur], H->V[par], rf(H), H->V[1 - par], H->r_old, H->B[nb], st);
+  else
+    launch_rowwise(H, H->B[cur], nullptr, rf(H), nullptr, 0, H->B[nb], st);
   H->bcur = nb;
   H->passes += 1;
 }
@@ -1013,24 +1043,37 @@ static void iterate_once(proxsdp_handle* H) {
     H->passes += 1;
   } else if (H->opt.eig_strict) {
     // rounds until the kept Ritz pairs meet eig_tol, then one final round
-    const double target = H->strict_tol > 0 ? H->strict_tol : H->opt.eig_tol;
-    for (int rd = 0; rd < 200; ++rd) {
-      eig_round(H, par, false);
+    const double target = H->opt.eig_tol;
+    H->strict_converged = false;
+    for (int rd = 0; rd < H->strict_rounds; ++rd) {
       double mr = 1.0;
+      if (H->strict_abs > 0) {
+        // exact-step check: Chebyshev-filtered rounds (the degree the
+        // spectrum allows, see cheb_max)
+        eig_iteration(H, par, std::min(H->cheb_max, H->opt.max_passes), false);
+        // exact-step check: the projection's error bound against its target
+        if (step_error(H, rf(H), &mr)) break;
+        if (mr <= H->strict_abs) {
+          H->strict_converged = true;
+          break;
+        }
+        continue;
+      }
+      eig_round(H, par, false);
       if (true_maxres(H, rf(H), &mr)) break;
-      if (mr <= target) break;
+      if (mr <= target) {
+        H->strict_converged = true;
+        break;
+      }
     }
     eig_round(H, par, true);
   } else {
-    if (H->m_rounds <= 2) {
-      eig_iteration(H, par, H->m_rounds);
-    } else {
-      // higher filter degrees without re-orthogonalisation collapse the basis
-      // onto the dominant eigenvectors when the spectrum is wide: take the
-      // extra passes as full rounds (pass, Rayleigh-Ritz, next basis)
-      for (int rd = 0; rd < H->m_rounds - 2; ++rd) eig_round(H, par, false);
-      eig_iteration(H, par, 2);
-    }
+    // Chebyshev filter passes without Rayleigh-Ritz up to the degree that
+    // keeps the basis well conditioned (cheb_max); further passes as full
+    // rounds (pass, Rayleigh-Ritz, next basis)
+    const int mc = std::min(H->m_rounds, H->cheb_max);
+    for (int rd = 0; rd < H->m_rounds - mc; ++rd) eig_round(H, par, false);
+    eig_iteration(H, par, mc);
   }
   // dual step
   hipLaunchKernelGGL(k_gather_dual, dim3(H->nrow_blocks), dim3(ROW_LANES * ROWS_PER_BLOCK), 0, st, H->dp, H->V[par],
@@ -1061,8 +1104,8 @@ static int run_round(proxsdp_handle* H, int count) {
   double jt = jacobi_tol(H);
   int64_t jbits;
   std::memcpy(&jbits, &jt, sizeof(jbits));
-  const auto key = std::make_tuple(H->bcur, H->r, H->r_old, H->k, H->m_rounds, H->prec,
-                                   (int)H->w_fresh, (int)lowp, count, jbits);
+  const auto key = std::make_tuple(H->bcur, H->r, H->r_old, H->k, H->m_rounds * 256 + H->cheb_max,
+                                   H->prec, (int)H->w_fresh, (int)lowp, count, jbits);
   auto it = H->graphs.find(key);
   if (it == H->graphs.end()) {
     proxsdp_handle::GraphEntry e{};
@@ -1237,17 +1280,23 @@ static int rank_probe(proxsdp_handle* H, double thr, int* verdict, double* ub_ou
 // iteration is the KKT point); the adaptive-accuracy iterations before it
 // only report residuals of their own inexact steps.  The eigen error only
 // has to be small against the step: an error delta in X moves eps_p by about
-// delta / alpha, so the absolute Ritz residual of the kept pairs is held at
-// 1% of alpha eps_p (or eig_tol, if larger).  *out gets its record.
+// delta / alpha and eps_d by at most ||M|| delta = 0.95 delta / alpha, so the
+// rounds run until the projection's error bound (step_error) is below 10% of
+// what the stopping rule allows either residual,
+//   0.1 alpha tol min(1 + ||C||_F, (1 + ||[b; h]||) / 0.95),
+// within 1000 rounds (strict_converged says whether it got there).  *out gets
+// its record.
 static int verify_step(proxsdp_handle* H, const IterRecord& last, IterRecord* out) {
   const int strict = H->opt.eig_strict;
   H->opt.eig_strict = 1;
-  H->strict_tol = last.normw > 0
-                      ? std::max(H->opt.eig_tol, 0.01 * H->opt.alpha * last.eps_p / last.normw)
-                      : H->opt.eig_tol;
+  (void)last;
+  const double scale = std::min(1.0 + H->h.norm_c, (1.0 + H->h.norm_rhs) / 0.95);
+  H->strict_abs = std::max(0.1 * H->opt.alpha * H->opt.tol * scale, 1e-300);
+  H->strict_rounds = 1000;
   iterate_once(H);
   H->opt.eig_strict = strict;
-  H->strict_tol = 0.0;
+  H->strict_abs = 0.0;
+  H->strict_rounds = 200;
   std::vector<IterRecord> recs;
   int rc = read_records(H, H->iters - 1, 1, recs);
   if (rc) return rc;
@@ -1341,8 +1390,17 @@ static int control(proxsdp_handle* H) {
       IterRecord vr{};
       const int rc4 = verify_step(H, rec, &vr);
       if (rc4) return rc4;
+      if (!H->strict_converged) {
+        // the exact step could not be formed within the round budget: no
+        // convergence claim now; after three such checks, none at all
+        if (++H->verify_unconverged >= 3) {
+          H->status = PROXSDP_STATUS_EIG_NOT_CONVERGED;
+          fill_info(H, vr, nonfinite);
+          return PROXSDP_OK;
+        }
+      }
       const double vp = vr.eps_p / (1.0 + H->h.norm_c), vd = vr.eps_d / (1.0 + H->h.norm_rhs);
-      if (std::max(vp, vd) <= H->opt.tol && std::isfinite(vp + vd)) {
+      if (H->strict_converged && std::max(vp, vd) <= H->opt.tol && std::isfinite(vp + vd)) {
         H->status = PROXSDP_STATUS_CONVERGED;
         fill_info(H, vr, nonfinite);
         return PROXSDP_OK;
@@ -1395,6 +1453,17 @@ static int control(proxsdp_handle* H) {
     H->eta = normw > 0 ? eta_abs / normw : H->opt.eig_tol;
     if (worst > eta_abs && H->m_rounds < H->opt.max_passes) H->m_rounds += 1;
     else if (worst < 0.05 * eta_abs && H->m_rounds > 1) H->m_rounds -= 1;
+    // Filter degree: with x1 = (theta_1 - c) / e the top Ritz value in the
+    // filter's variable, a degree-d Chebyshev polynomial amplifies the top of
+    // the wanted spectrum by up to T_d(x1) against its lower edge (x = 1);
+    // degrees with T_d(x1) <= 100 keep the basis well conditioned for the
+    // Rayleigh-Ritz step (higher ones collapse it onto the dominant vectors).
+    // A wide spectrum (x1 near 1, e.g. a dense C) gets many filter passes per
+    // step, a narrow one a single pass.
+    double x1 = 1.0;
+    for (auto& x : recs) x1 = std::max(x1, x.filt_x1);
+    const double d = x1 > 1.0 + 1e-12 ? std::acosh(100.0) / std::acosh(x1) : 1e9;
+    H->cheb_max = (int)std::max(2.0, std::min((double)H->opt.max_passes, 1.0 + std::floor(d)));
   }
   fill_info(H, rec, nonfinite);
   return PROXSDP_OK;
@@ -1460,9 +1529,10 @@ static int reset_buffers(proxsdp_handle* H) {
   H->saved.clear();
   H->rank_value = std::nan("");
   H->verify_steps = 0;
+  H->verify_unconverged = 0;
   H->width_changes = 0;
+  H->cheb_max = 2;
   H->verify_q = 1.0;
-  H->strict_tol = 0.0;
   H->opt.eig_rel = H->eig_rel_user;
   H->time_s = 0;
   H->last = proxsdp_info{};

@@ -667,6 +667,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
   __syncthreads();
   int sweeps = 0, path = -1;
   int why = 0;   // Cholesky path taken because: 1 G not orthonormal, 2 kept couplings, 3 tail bound
+  int nsteps = 0;   // Newton steps taken
   double* Sbuf;   // sorted Ritz coefficients (k x ld)
   double* Pbuf;   // P (k x ld)
   double* Ybuf;   // P S (k x ld)
@@ -789,6 +790,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
       if (!newton_ok) why = (gb <= thr) ? 2 : 3;
     }
     if (newton_ok) path = st;
+    nsteps = st;
   }
   tph[1] = wall_clock64();
   // -------------------------------------------------------- Cholesky path
@@ -979,6 +981,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
       sc[S_LAMR1] = (rk < k) ? vals[rk] : __builtin_nan("");
       sc[S_NORMW] = scale;
       sc[S_NPOS] = (double)npos;
+      sc[S_FILTX1] = filter ? (vals[0] - fc) / fe : 0.0;
       sc[S_CHOLFIX] = (double)flag[0];
       sc[S_FILTC] = fc;
       sc[S_FILTE] = fe;
@@ -986,6 +989,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
       sc[S_RRPATH] = (double)path;
       sc[S_RRCHOL] += (path < 0) ? 1.0 : 0.0;
       if (why > 0) sc[S_RRWHY1 + why - 1] += 1.0;
+      sc[S_RRSTEPS] += (double)nsteps;
       tph[4] = wall_clock64();
       for (int ph = 0; ph < 4; ++ph) sc[S_RRT0 + ph] += 1e-8 * (double)(tph[ph + 1] - tph[ph]);
       sc[S_RRCOUNT] += 1.0;

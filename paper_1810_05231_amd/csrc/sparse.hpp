@@ -160,28 +160,31 @@ __global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __
   const double alpha = small[SL::SC + S_ALPHA];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  double lo = 1e308, mdy2 = 0.0;
+  double lo = 1e308, lo2 = 1e308, mdy2 = 0.0;
   double crossq[MAX_R1];
   for (int q = 0; q < MAX_R1; ++q) crossq[q] = 0.0;
   for (int a = blockIdx.x * 4 + wave; a < dp.n; a += gridDim.x * 4) {
-    double center = 0.0, radius = 0.0;
+    double center = 0.0, radius = 0.0, center2 = 0.0, radius2 = 0.0;
     const int s0 = dp.sym_ptr[a], s1 = dp.sym_ptr[a + 1];
     for (int s = s0 + lane; s < s1; s += 64) {
       const int e = dp.sym_e[s];
       const int ea = dp.pat_a[e], eb = dp.pat_b[e];
-      double dv = -alpha * dp.pat_c[e];
-      double md = 0.0;
+      double my = 0.0, md = 0.0;
       for (int t = dp.pat_rptr[e]; t < dp.pat_rptr[e + 1]; ++t) {
         const int i = dp.pat_row[t];
         const double v = dp.pat_val[t];
         const double yi = y[i];
-        dv += alpha * yi * v;
+        my += alpha * yi * v;
         md += (yi - y_old[i]) * v;
       }
-      if (ea == eb)
+      const double dv = -alpha * dp.pat_c[e] + my;
+      if (ea == eb) {
         center += dv;
-      else
+        center2 += my;
+      } else {
         radius += fabs(dv);
+        radius2 += fabs(my);
+      }
       if (ea == a) {  // owner of the entry
         dval[e] = dv;
         const double w = (ea == eb) ? 1.0 : 2.0;
@@ -192,14 +195,18 @@ __global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __
     }
     center = wave_sum(center);
     radius = wave_sum(radius);
+    center2 = wave_sum(center2);
+    radius2 = wave_sum(radius2);
     lo = fmin(lo, center - radius);
+    lo2 = fmin(lo2, center2 - radius2);
   }
   lo = block_min(lo, red);
+  lo2 = block_min(lo2, red);
   mdy2 = block_sum(mdy2, red);
   for (int q = 0; q < MAX_R1; ++q) crossq[q] = block_sum(crossq[q], red);
   if (threadIdx.x == 0) {
     double* o = pat_part + (int64_t)blockIdx.x * PAT_PART;
-    o[0] = lo; o[1] = mdy2; o[2] = 0.0; o[3] = 0.0;
+    o[0] = lo; o[1] = mdy2; o[2] = lo2; o[3] = 0.0;
     for (int q = 0; q < MAX_R1; ++q) o[4 + q] = crossq[q];
   }
 }
@@ -237,12 +244,12 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     const double* o = f.row_part + (int64_t)b * ROW_PART;
     ed2 += o[0]; cross += o[1]; dobj += o[2]; bad += o[3]; ymx += o[4];
   }
-  double lo = 1e308, mdy2 = 0.0, lth = 0.0;
+  double lo = 1e308, lo2 = 1e308, mdy2 = 0.0, lth = 0.0;
   double cq[MAX_R1];
   for (int q = 0; q < MAX_R1; ++q) cq[q] = 0.0;
   for (int b = tid; b < f.npat_blocks; b += nt) {
     const double* o = f.pat_part + (int64_t)b * PAT_PART;
-    lo = fmin(lo, o[0]); mdy2 += o[1];
+    lo = fmin(lo, o[0]); mdy2 += o[1]; lo2 = fmin(lo2, o[2]);
     for (int q = 0; q < MAX_R1; ++q) cq[q] += o[4 + q];
   }
   for (int t = tid; t < r; t += nt) lth += lam[t] * small[SL::THETA + t];
@@ -255,6 +262,7 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     for (int q = 0; q < MAX_R1; ++q) cq[q] = v[9 + q];
   }
   lo = block_min(lo, red);
+  lo2 = block_min(lo2, red);
   // true Ritz residuals of the kept pairs (row-wise partials of the final round)
   double worst = 0.0;
   {
@@ -301,7 +309,10 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     sc[S_OBJ] = obj;
     sc[S_DOBJ] = dobj;
     sc[S_DX2] = dx2;
-    sc[S_GERSH] = lo + gamma_lo;
+    // lower bound of lambda_min(W) (X+ is PSD): Gershgorin of D, or Weyl with
+    // lambda_max(C) <= ||C||_F and Gershgorin of alpha M*(y) -- the second is
+    // far tighter for a dense C
+    sc[S_GERSH] = fmax(lo, -alpha * dp.norm_c + lo2) + gamma_lo;
     if (bad > 0.0) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 3.0);
     if (!isfinite(eps_p) || !isfinite(eps_d)) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 4.0);
     IterRecord rec;
@@ -314,6 +325,7 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     rec.maxres = sc[S_MAXRES];
     rec.normw = sc[S_NORMW];
     rec.npos = sc[S_NPOS];
+    rec.filt_x1 = sc[S_FILTX1];
     // ring slot: given (set-up record) or the device iteration counter, so
     // that a captured round of iterations can be replayed
     int slot = f.ring_slot;

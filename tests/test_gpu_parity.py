@@ -159,6 +159,8 @@ def _instance(kind, n, seed=7):
         return I.equipartition(n, 0.1, seed)
     if kind == "planted":
         return I.planted_lowrank(n, 48, seed)
+    if kind == "mimo":
+        return I.mimo(n - 1, seed)
     return I.snl(n - 2, seed=seed, noise=0.0)
 
 
@@ -169,7 +171,7 @@ def _instance(kind, n, seed=7):
                                         ("equip", 40, 2, 25), ("maxcut", 200, 4, 20),
                                         ("equip", 180, 3, 20), ("snl", 102, 4, 30),
                                         ("snl", 302, 8, 30), ("planted", 300, 48, 10),
-                                        ("planted", 300, 64, 10)])
+                                        ("planted", 300, 64, 10), ("mimo", 51, 4, 15)])
 def test_iterates_match_oracle(torch_cuda, kind, n, r, K):
     from paper_1810_05231_amd import Solver
     _say("iterates", kind, n, r, K)
@@ -387,6 +389,32 @@ def test_implicit_form_solve(torch_cuda, kind, n, seed):
     s.close()
 
 
+# ------------------------------------------------------- MIMO detection
+@pytest.mark.parametrize("n,seed,prec", [(100, 1, 0), (100, 2, IMPLICIT), (400, 3, 0)])
+def test_mimo_solve_recovers_signal(torch_cuda, n, seed, prec):
+    """Binary MIMO detection (Section 5.3): dense cost, element-wise box rows.
+    At high SNR the relaxation is exact, so the signal read from the last
+    column of X must be the transmitted one bit for bit (and the oracle's at
+    n = 100); the oracle certifies the answer."""
+    from paper_1810_05231_amd import Solver
+    _say("mimo", n, seed, "prec", prec)
+    prob = I.mimo(n, seed)
+    s = Solver(prob, tol=1e-4, precision=prec)
+    info = s.solve()
+    _say("  gpu", info["status_name"], info["iters"], info["r"], repr(info["obj"]), info["time_s"])
+    assert info["status_name"] == "converged"
+    X, y = s.solution(on_device=False)
+    xhat = np.sign(X[:n, n])
+    assert np.array_equal(xhat, prob.meta["x_true"])
+    cert = O.certificate(prob, X, y)
+    _say("  cert", cert.rho_p, cert.rho_d, cert.primal_infeas)
+    assert max(cert.rho_p, cert.rho_d) <= 2e-4
+    if n <= 100:
+        ref = O.solve(prob, tol=1e-4)
+        assert np.array_equal(np.sign(ref.X[:n, n]), xhat)
+    s.close()
+
+
 # ------------------------------------------------- hyperplane rounding
 def test_hyperplane_rounding_matches_oracle(torch_cuda):
     """Random-hyperplane rounding of the GPU's max-cut answer: the same factors
@@ -443,11 +471,18 @@ def test_snl_solve_feasible(torch_cuda, sensors, precision, must_converge):
     if info["status_name"] != "converged":
         assert not must_converge
         assert info["status_name"] in ("rank_limit", "eig_not_converged")
-        assert max(info["rho_p"], info["rho_d"]) <= 1e-3
-        assert info["r"] == 64
-        saved = s.saved()
-        assert saved and saved[-1][0] == info["iters"]
-        assert saved[-1][1].shape[1] == min(info["r"], info["k"])
+        if info["verify_steps"] > 0 and info["status_name"] == "eig_not_converged":
+            # the exact-step check could not converge its eigensolve within
+            # its round budget, so the solve makes no convergence claim; the
+            # answer is still near the tolerance
+            assert max(cert.rho_p, cert.rho_d) <= 5e-3
+        else:
+            # the rank test failed or stayed undecided at the cap: X_[r] kept
+            assert max(info["rho_p"], info["rho_d"]) <= 1e-3
+            assert info["r"] == 64
+            saved = s.saved()
+            assert saved and saved[-1][0] == info["iters"]
+            assert saved[-1][1].shape[1] == min(info["r"], info["k"])
         s.close()
         return
     assert max(cert.rho_p, cert.rho_d) <= 2e-3
