@@ -318,6 +318,8 @@ def main():
                                     "tail_bound": int(dbg["rr_chol_tail"])},
             "verify_steps": last["verify_steps"],
             "rr_newton_steps_per_call": round(dbg["rr_newton_steps_total"] / max(dbg["rr_calls"], 1), 2),
+            "rr_newton_capped_calls": int(dbg["rr_newton_capped"]),
+            "rr_jacobi_sweeps_after_newton": int(dbg["rr_newton_jacobi_sweeps"]),
             "rr_phase_s": {"newton": round(dbg["rr_t_newton"], 4), "cholesky": round(dbg["rr_t_cholesky"], 4),
                            "diagonalise": round(dbg["rr_t_diag"], 4), "output": round(dbg["rr_t_out"], 4)},
         },

@@ -374,7 +374,9 @@ int proxsdp_rank_path(proxsdp_handle *h, int32_t *iters, int32_t *ranks, int32_t
  * the Rayleigh-Ritz steps spent in their Newton refinement / Cholesky path /
  * diagonalisation / coefficient output, from the device clock, 29 positive
  * kept Ritz values, 30 the top Ritz value in the filter's variable, 31 Newton
- * refinement steps of all Rayleigh-Ritz calls) followed by the Ritz values of the last
+ * refinement steps of all Rayleigh-Ritz calls, 32 calls whose refinement
+ * reached its step limit, 33 Jacobi sweeps after accepted refinements) followed
+ * by the Ritz values of the last
  * Rayleigh-Ritz step in out[64 ..] if count > 64.  Synchronises. */
 int proxsdp_debug_scalars(proxsdp_handle *h, double *out, int32_t count);
 

@@ -76,6 +76,8 @@ enum Scalar {
   S_NPOS,         // leading positive Ritz values among the kept ones (last Rayleigh-Ritz)
   S_FILTX1,       // (theta_1 - c) / e: the largest Ritz value in the filter's scaled variable
   S_RRSTEPS,      // Newton refinement steps of all Rayleigh-Ritz calls since create/reset
+  S_RRCAP,        // Rayleigh-Ritz calls whose Newton steps reached the step limit
+  S_RRJSW,        // Jacobi sweeps after an accepted Newton path (summed)
   S_COUNT
 };
 

@@ -283,61 +283,88 @@ __global__ __launch_bounds__(512) void k_reduce_gram(const double* __restrict__ 
   const int64_t base = (int64_t)s * SLICE * k;
   const int cnt = SLICE * k;
   const int64_t cstride = (int64_t)npad * k;
-  // pairs of elements (16-byte loads); the chunk partials of each element are
-  // summed in chunk order with eight loads in flight at a time
-  for (int t = 2 * threadIdx.x; t < cnt; t += 2 * blockDim.x) {
-    const int64_t off = base + t;
-    double2 z = make_double2(0.0, 0.0);
-    for (int c = 0; c < nchunks; c += 8) {
-      double2 v[8];
+  // pairs of elements (16-byte loads), RG_PAIRS per thread; the chunk partials
+  // of all of a thread's pairs are loaded RG_BATCH chunks at a time before any
+  // is added (one memory latency per batch, not per pair), and each element is
+  // summed in chunk order
+  constexpr int RG_PAIRS = SLICE * KMAX / 2 / 512, RG_BATCH = 4;
+  int tt[RG_PAIRS];
+  double2 z[RG_PAIRS], b[RG_PAIRS], bp[RG_PAIRS];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        v[u] = (c + u < nchunks) ? *reinterpret_cast<const double2*>(part + (c + u) * cstride + off)
-                                 : make_double2(0.0, 0.0);
+  for (int j = 0; j < RG_PAIRS; ++j) {
+    tt[j] = 2 * ((int)threadIdx.x + j * (int)blockDim.x);
+    z[j] = make_double2(0.0, 0.0);
+    const bool in = tt[j] < cnt;
+    b[j] = in ? *reinterpret_cast<const double2*>(B + base + tt[j]) : make_double2(0.0, 0.0);
+    bp[j] = (in && cheb == 2) ? *reinterpret_cast<const double2*>(Bprev + base + tt[j])
+                              : make_double2(0.0, 0.0);
+  }
+  for (int c = 0; c < nchunks; c += RG_BATCH) {
+    double2 v[RG_BATCH][RG_PAIRS];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < RG_BATCH; ++u)
+#pragma unroll
+      for (int j = 0; j < RG_PAIRS; ++j)
+        v[u][j] = (c + u < nchunks && tt[j] < cnt)
+                      ? *reinterpret_cast<const double2*>(part + (c + u) * cstride + base + tt[j])
+                      : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < RG_BATCH; ++u)
+#pragma unroll
+      for (int j = 0; j < RG_PAIRS; ++j)
         if (c + u < nchunks) {
-          z.x += v[u].x;
-          z.y += v[u].y;
+          z[j].x += v[u][j].x;
+          z[j].y += v[u][j].y;
         }
-    }
-    const double2 b = *reinterpret_cast<const double2*>(B + off);
+  }
+#pragma unroll
+  for (int j = 0; j < RG_PAIRS; ++j) {
+    const int t = tt[j];
+    if (t >= cnt) continue;
     if (cheb == 1) {
-      z.x = (z.x - cc * b.x) / ce;
-      z.y = (z.y - cc * b.y) / ce;
+      z[j].x = (z[j].x - cc * b[j].x) / ce;
+      z[j].y = (z[j].y - cc * b[j].y) / ce;
     } else if (cheb == 2) {
-      const double2 bp = *reinterpret_cast<const double2*>(Bprev + off);
-      z.x = 2.0 * (z.x - cc * b.x) / ce - bp.x;
-      z.y = 2.0 * (z.y - cc * b.y) / ce - bp.y;
+      z[j].x = 2.0 * (z[j].x - cc * b[j].x) / ce - bp[j].x;
+      z[j].y = 2.0 * (z[j].y - cc * b[j].y) / ce - bp[j].y;
     }
-    if (Z) *reinterpret_cast<double2*>(Z + off) = z;
-    sZ[t] = z.x;
-    sZ[t + 1] = z.y;
-    sB[t] = b.x;
-    sB[t + 1] = b.y;
+    if (Z) *reinterpret_cast<double2*>(Z + base + t) = z[j];
+    sZ[t] = z[j].x;
+    sZ[t + 1] = z[j].y;
+    sB[t] = b[j].x;
+    sB[t + 1] = b[j].y;
   }
   if (!grams) return;
   __syncthreads();
   gram_blocks_mfma(sB, sZ, k, gram_part + (int64_t)s * 3 * k * k);
 }
 
-// Per slice of SLICE rows (all products on MFMA f64 16x16x4):
-//   Vs = B S[:, :rp], ZS = Z S[:, :rp]   (Ritz vectors and W times them; rp = r rounded to 16)
-//   residual partials ||ZS_c - theta_c Vs_c||^2 over the slice -> fac_part[FAC_RES + c], c < r
-//   V = Vs[:, :r] (row stride KMAX)                              if V
-//   Bn = Z MZ + B MB (row stride k)                              if Bn
-//   factor partials [V^T V | V^T Vold | u_q^T V]                 if V
+// Per slice of SLICE rows (all products on MFMA f64 16x16x4), in three kinds of
+// workgroup (blockIdx.y) that run side by side:
+//   0 factors    Vs = B S[:, :rp] (rp = r rounded to 16); V = Vs[:, :r] (row
+//                stride KMAX); partials of [V^T V | V^T Vold | u_q^T V]   (if V)
+//   1 basis      Bn = Z MZ + B MB (row stride k)                          (if Bn)
+//   2 residuals  Vs and ZS = Z S[:, :rp]; partials ||ZS_c - theta_c Vs_c||^2
+//                -> fac_part[FAC_RES + c], c < r
+// (Vs is formed by kinds 0 and 2 alike, by the same code.)
 // LDS: B, Z with row stride k + 1 and Vs, ZS with row stride rp + 1 (odd
 // strides keep the 16 lanes of an MFMA operand column on distinct banks).
-__device__ inline d4 mfma_rows_times_small(const double* Xl, int ldx, int row0,
-                                           const double* Sg, int ldS, int col0, int k, d4 acc) {
-  // acc[m][n] += sum_q Xl[row0 + m][q] * Sg[q][col0 + n]; the global operand
-  // column is loaded whole before the products (one memory latency per job)
+// Operand columns of the small matrices (S, MZ, MB) are loaded from global
+// memory once per wave and column block: with 8 waves and at most 4 column
+// blocks every job of a wave shares one.
+__device__ inline void load_small_col(const double* Sg, int ldS, int col0, int k,
+                                      double (&bq)[KMAX / 4]) {
   const int lane = threadIdx.x & 63;
   const int m = lane & 15, kq = lane >> 4;
-  double bq[KMAX / 4];
 #pragma unroll
   for (int q = 0; q < KMAX / 4; ++q) bq[q] = (4 * q < k) ? Sg[(4 * q + kq) * ldS + col0 + m] : 0.0;
+}
+
+__device__ inline d4 mfma_rows_times_cols(const double* Xl, int ldx, int row0,
+                                          const double (&bq)[KMAX / 4], int k, d4 acc) {
+  // acc[m][n] += sum_q Xl[row0 + m][q] * S[q][col0 + n], S's column block in bq
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int q = 0; q < KMAX / 4; ++q) {
     if (4 * q < k) {
@@ -365,17 +392,33 @@ __global__ __launch_bounds__(512) void k_rowwise(const double* __restrict__ B,
   double* sZS = sV + SLICE * ldr;    // SLICE x ldr
   double* sU = sZS + SLICE * ldr;    // n_r1 x SLICE: rank-one vectors on the slice
   const int s = blockIdx.x;
-  // blockIdx.y == 1: the next basis only; blockIdx.y == 0: everything else
-  const bool part_bn = blockIdx.y == 1;
-  if (part_bn && !Bn) return;
+  const int kind = blockIdx.y;
+  if ((kind == 0 && !V) || (kind == 1 && !Bn)) return;
+  const bool needZ = kind != 0;
   const int i0 = s * SLICE;
   const int64_t base = (int64_t)i0 * k;
-  for (int t = threadIdx.x; t < SLICE * k; t += blockDim.x) {
-    const int i = t / k, c = t - (t / k) * k;
-    sB[i * ldk + c] = B[base + t];
-    sZ[i * ldk + c] = Z[base + t];
+  {
+    // all loads of the slice in flight together (blockDim.x = 512)
+    constexpr int PER = SLICE * KMAX / 512;
+    const int cnt = SLICE * k;
+    double vb[PER], vz[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int t = threadIdx.x + j * 512;
+      vb[j] = t < cnt ? B[base + t] : 0.0;
+      vz[j] = (needZ && t < cnt) ? Z[base + t] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int t = threadIdx.x + j * 512;
+      if (t < cnt) {
+        const int i = t / k, c = t - (t / k) * k;
+        sB[i * ldk + c] = vb[j];
+        if (needZ) sZ[i * ldk + c] = vz[j];
+      }
+    }
   }
-  if (V && !part_bn)
+  if (kind == 0)
     for (int t = threadIdx.x; t < n_r1 * SLICE; t += blockDim.x)
       sU[t] = r1_u[(int64_t)(t / SLICE) * npad + i0 + (t % SLICE)];
   __syncthreads();
@@ -385,81 +428,105 @@ __global__ __launch_bounds__(512) void k_rowwise(const double* __restrict__ B,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int m = lane & 15, kq = lane >> 4;
   const int rb = rp / 16, kb = k / 16;
-  // jobs: [Vs blocks: 4 x rb] [ZS blocks: 4 x rb] [Bn blocks: 4 x kb]
-  const int nV = part_bn ? 0 : 4 * rb, nBn = part_bn ? 4 * kb : 0;
-  for (int job = wave; job < 2 * nV + nBn; job += nw) {
-    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-    if (job < 2 * nV) {
-      const bool isZ = job >= nV;
-      const int jb = isZ ? job - nV : job;
-      const int row0 = (jb / rb) * 16, col0 = (jb - (jb / rb) * rb) * 16;
-      acc = mfma_rows_times_small(isZ ? sZ : sB, ldk, row0, S, KMAX, col0, k, acc);
-      double* dst = isZ ? sZS : sV;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = row0 + kq + 4 * v, col = col0 + m;
-        dst[row * ldr + col] = acc[v];
-        if (!isZ && V && col < r) V[(int64_t)(i0 + row) * KMAX + col] = acc[v];
+  double bq[KMAX / 4], bq2[KMAX / 4];
+  int cached = -1;
+  if (kind == 1) {
+    // jobs: Bn blocks (4 x kb)
+    for (int job = wave; job < 4 * kb; job += nw) {
+      const int row0 = (job / kb) * 16, col0 = (job - (job / kb) * kb) * 16;
+      if (col0 != cached) {
+        load_small_col(MZ, KMAX, col0, k, bq);
+        load_small_col(MB, KMAX, col0, k, bq2);
+        cached = col0;
       }
-    } else {
-      const int jb = job - 2 * nV;
-      const int row0 = (jb / kb) * 16, col0 = (jb - (jb / kb) * kb) * 16;
-      acc = mfma_rows_times_small(sZ, ldk, row0, MZ, KMAX, col0, k, acc);
-      acc = mfma_rows_times_small(sB, ldk, row0, MB, KMAX, col0, k, acc);
+      d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+      acc = mfma_rows_times_cols(sZ, ldk, row0, bq, k, acc);
+      acc = mfma_rows_times_cols(sB, ldk, row0, bq2, k, acc);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + kq + 4 * v, col = col0 + m;
         Bn[base + (int64_t)row * k + col] = acc[v];
       }
     }
+    return;
   }
-  if (part_bn) return;
+  // jobs: [Vs blocks: 4 x rb] (+ [ZS blocks: 4 x rb] for the residuals)
+  const int nV = 4 * rb;
+  const int njobs = kind == 2 ? 2 * nV : nV;
+  for (int job = wave; job < njobs; job += nw) {
+    const bool isZ = job >= nV;
+    const int jb = isZ ? job - nV : job;
+    const int row0 = (jb / rb) * 16, col0 = (jb - (jb / rb) * rb) * 16;
+    if (col0 != cached) {
+      load_small_col(S, KMAX, col0, k, bq);
+      cached = col0;
+    }
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    acc = mfma_rows_times_cols(isZ ? sZ : sB, ldk, row0, bq, k, acc);
+    double* dst = isZ ? sZS : sV;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + kq + 4 * v, col = col0 + m;
+      dst[row * ldr + col] = acc[v];
+      if (kind == 0 && col < r) V[(int64_t)(i0 + row) * KMAX + col] = acc[v];
+    }
+  }
   __syncthreads();
   double* out = fac_part + (int64_t)s * FAC_STRIDE;
-  const double* theta = small + SL::THETA;
-  // residual norms: eight lanes per column, SLICE / 8 rows each, combined by
-  // a fixed butterfly
-  for (int c0 = 0; c0 < r; c0 += (int)blockDim.x / 8) {
-    const int c = c0 + (int)(threadIdx.x >> 3), part = threadIdx.x & 7;
-    const int cc = c < r ? c : 0;
-    const double th = theta[cc];
-    double acc = 0.0;
+  if (kind == 2) {
+    const double* theta = small + SL::THETA;
+    // residual norms: eight lanes per column, SLICE / 8 rows each, combined by
+    // a fixed butterfly
+    for (int c0 = 0; c0 < r; c0 += (int)blockDim.x / 8) {
+      const int c = c0 + (int)(threadIdx.x >> 3), part = threadIdx.x & 7;
+      const int cc = c < r ? c : 0;
+      const double th = theta[cc];
+      double acc = 0.0;
 #pragma unroll
-    for (int j = 0; j < SLICE / 8; ++j) {
-      const int i = part * (SLICE / 8) + j;
-      const double d = sZS[i * ldr + cc] - th * sV[i * ldr + cc];
-      acc += d * d;
+      for (int j = 0; j < SLICE / 8; ++j) {
+        const int i = part * (SLICE / 8) + j;
+        const double d = sZS[i * ldr + cc] - th * sV[i * ldr + cc];
+        acc += d * d;
+      }
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      acc += __shfl_xor(acc, 4);
+      if (c < r && part == 0) out[FAC_RES + c] = acc;
     }
-    acc += __shfl_xor(acc, 1);
-    acc += __shfl_xor(acc, 2);
-    acc += __shfl_xor(acc, 4);
-    if (c < r && part == 0) out[FAC_RES + c] = acc;
+    return;
   }
-  if (!V) return;
   // factor Grams on MFMA: V^T V (rb x rb blocks) and V^T Vold (rb x rob blocks)
   const int rop = (r_old + 15) & ~15;
   const int rob = rop / 16;
   const int n1 = r * r;
+  int cached_old = -1;
+  double bo[SLICE / 4];
   for (int job = wave; job < rb * rb + rb * rob; job += nw) {
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
     const bool old = job >= rb * rb;
     const int jb = old ? job - rb * rb : job;
     const int nbk = old ? rob : rb;
     const int a0 = (jb / nbk) * 16, b0 = (jb - (jb / nbk) * nbk) * 16;
-    double bq[SLICE / 4];
     if (old) {
-      const bool in = b0 + m < r_old;
+      if (b0 != cached_old) {
+        const bool in = b0 + m < r_old;
 #pragma unroll
-      for (int q = 0; q < SLICE / 4; ++q)
-        bq[q] = in ? Vold[(int64_t)(i0 + 4 * q + kq) * KMAX + b0 + m] : 0.0;
+        for (int q = 0; q < SLICE / 4; ++q)
+          bo[q] = in ? Vold[(int64_t)(i0 + 4 * q + kq) * KMAX + b0 + m] : 0.0;
+        cached_old = b0;
+      }
+#pragma unroll
+      for (int q = 0; q < SLICE / 4; ++q) {
+        const double a = sV[(4 * q + kq) * ldr + a0 + m];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bo[q], acc, 0, 0, 0);
+      }
     } else {
 #pragma unroll
-      for (int q = 0; q < SLICE / 4; ++q) bq[q] = sV[(4 * q + kq) * ldr + b0 + m];
-    }
-#pragma unroll
-    for (int q = 0; q < SLICE / 4; ++q) {
-      const double a = sV[(4 * q + kq) * ldr + a0 + m];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq[q], acc, 0, 0, 0);
+      for (int q = 0; q < SLICE / 4; ++q) {
+        const double a = sV[(4 * q + kq) * ldr + a0 + m];
+        const double bv = sV[(4 * q + kq) * ldr + b0 + m];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {

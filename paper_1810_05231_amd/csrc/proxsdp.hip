@@ -753,7 +753,7 @@ static void launch_reduce(const double* part, int nchunks, double* Z, const doub
 static void launch_rr(const double* gram_part, int nsl, double* small, int k, int r, int lam_off,
                       int filter, double jac_tol, hipStream_t st, int oa_steps = 10) {
   const int kk = k * k;
-  hipLaunchKernelGGL(k_sum_grams, dim3((4 * 3 * kk + 255) / 256), dim3(256), 0, st, gram_part, nsl, k,
+  hipLaunchKernelGGL(k_sum_grams, dim3((SG_LANES * 3 * kk + 255) / 256), dim3(256), 0, st, gram_part, nsl, k,
                      small);
   const size_t lds = small_rr_lds_doubles(k) * sizeof(double) + (2 * KMAX + 4) * sizeof(int);
 #define RR_LAUNCH(KQ)                                                                    \
@@ -773,7 +773,7 @@ static void launch_rowwise(proxsdp_handle* H, const double* B, double* V, int r,
   const int rp = (r + 15) & ~15;
   const size_t lds = (2 * (size_t)SLICE * (H->k + 1) + 2 * (size_t)SLICE * (rp + 1) +
                       (size_t)MAX_R1 * SLICE) * sizeof(double);
-  hipLaunchKernelGGL(k_rowwise, dim3(H->nsl, Bn ? 2 : 1), dim3(512), lds, st, B, H->Z, H->small, H->k, V, r,
+  hipLaunchKernelGGL(k_rowwise, dim3(H->nsl, 3), dim3(512), lds, st, B, H->Z, H->small, H->k, V, r,
                      Vold, r_old, Bn, H->dp.n_r1, H->dp.r1_u, H->npad, H->fac_part);
 }
 

@@ -990,6 +990,8 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
       sc[S_RRCHOL] += (path < 0) ? 1.0 : 0.0;
       if (why > 0) sc[S_RRWHY1 + why - 1] += 1.0;
       sc[S_RRSTEPS] += (double)nsteps;
+      sc[S_RRCAP] += (nsteps >= oa_steps && oa_steps > 0) ? 1.0 : 0.0;
+      if (newton_ok) sc[S_RRJSW] += (double)sweeps;
       tph[4] = wall_clock64();
       for (int ph = 0; ph < 4; ++ph) sc[S_RRT0 + ph] += 1e-8 * (double)(tph[ph + 1] - tph[ph]);
       sc[S_RRCOUNT] += 1.0;
@@ -1000,20 +1002,30 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
 #undef RR_FOR_KK
 
 // Sums the per-slice Gram partials [B^T B, B^T Z, Z^T Z] into the GG/TG/PG
-// slots of `small`: four lanes per entry, each summing every fourth slice,
-// combined by a fixed butterfly (fixed summation order).
+// slots of `small`: SG_LANES lanes per entry, each summing every SG_LANES-th
+// slice with SG_BATCH loads in flight, combined by a fixed butterfly (fixed
+// summation order).
+constexpr int SG_LANES = 8, SG_BATCH = 8;
 __global__ __launch_bounds__(256) void k_sum_grams(const double* __restrict__ gram_part,
                                                    int nslices, int k, double* __restrict__ small) {
   const int kk = k * k;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const int t = g >> 2, part = g & 3;
+  const int t = g / SG_LANES, part = g % SG_LANES;
   double acc = 0.0;
   if (t < 3 * kk) {
-#pragma unroll 8
-    for (int s = part; s < nslices; s += 4) acc += gram_part[(int64_t)s * 3 * kk + t];
+    for (int s0 = part; s0 < nslices; s0 += SG_LANES * SG_BATCH) {
+      double v[SG_BATCH];
+#pragma unroll
+      for (int u = 0; u < SG_BATCH; ++u) {
+        const int s = s0 + u * SG_LANES;
+        v[u] = s < nslices ? gram_part[(int64_t)s * 3 * kk + t] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < SG_BATCH; ++u) acc += v[u];
+    }
   }
-  acc += __shfl_xor(acc, 1);
-  acc += __shfl_xor(acc, 2);
+#pragma unroll
+  for (int o = 1; o < SG_LANES; o <<= 1) acc += __shfl_xor(acc, o);
   if (t < 3 * kk && part == 0) {
     const int which = t / kk;
     small[SL::GG + which * SL::kk + (t - which * kk)] = acc;

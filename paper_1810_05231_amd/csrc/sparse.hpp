@@ -75,15 +75,29 @@ __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double
   __shared__ double red[16];
   // reduce the factor partials over the slices for the finalisation:
   // [V^T V (r x r) | V^T Vold (r x r_old)] -> small[FR ..], residuals -> small[FR + FAC_RES ..]
+  // (FR_LANES lanes per value, each summing every FR_LANES-th slice with
+  // FR_BATCH loads in flight, then a fixed butterfly)
   {
+    constexpr int FR_LANES = 8, FR_BATCH = 10;
     const int nfac = r * r + r * r_old;
     const int gsz = gridDim.x * blockDim.x;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nfac + r; t += gsz) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < (nfac + r) * FR_LANES; g += gsz) {
+      const int t = g / FR_LANES, part = g % FR_LANES;
       const int src = (t < nfac) ? t : FAC_RES + (t - nfac);
       double acc = 0.0;
-#pragma unroll 8
-      for (int s = 0; s < nslices; ++s) acc += fac_part[(int64_t)s * FAC_STRIDE + src];
-      small[SL::FR + src] = acc;
+      for (int s0 = part; s0 < nslices; s0 += FR_LANES * FR_BATCH) {
+        double v[FR_BATCH];
+#pragma unroll
+        for (int u = 0; u < FR_BATCH; ++u) {
+          const int s = s0 + u * FR_LANES;
+          v[u] = s < nslices ? fac_part[(int64_t)s * FAC_STRIDE + src] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < FR_BATCH; ++u) acc += v[u];
+      }
+#pragma unroll
+      for (int o = 1; o < FR_LANES; o <<= 1) acc += __shfl_xor(acc, o);
+      if (part == 0) small[SL::FR + src] = acc;
     }
   }
   const double* lam = small + lam_off;

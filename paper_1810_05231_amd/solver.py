@@ -198,7 +198,8 @@ class Solver:
                  18: "rr_newton_steps", 19: "rr_cholesky_calls", 20: "rr_calls",
                  22: "rr_chol_gram", 23: "rr_chol_couplings", 24: "rr_chol_tail",
                  25: "rr_t_newton", 26: "rr_t_cholesky", 27: "rr_t_diag", 28: "rr_t_out",
-                 29: "npos", 30: "filter_x1", 31: "rr_newton_steps_total"}
+                 29: "npos", 30: "filter_x1", 31: "rr_newton_steps_total",
+                 32: "rr_newton_capped", 33: "rr_newton_jacobi_sweeps"}
         d = {v: float(out[k]) for k, v in names.items()}
         d["theta"] = out[64:].tolist()
         return d
