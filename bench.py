@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--arpack-iters", type=int, default=1,
+                    help="iterations of the ARPACK-style CPU baseline (0 = skip)")
     ap.add_argument("--iters", type=int, default=0, help="run K iterations instead of a solve")
     ap.add_argument("--copy-calibration", type=int, default=0, help="MiB of a plain device copy")
     ap.add_argument("--window", type=int, default=0, help="Algorithm 2 window l (0 = library default)")
@@ -284,6 +286,9 @@ def main():
     check_block = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, last["iters"], args.cpu_iters)
+        if args.arpack_iters > 0:
+            cpu["arpack_style"] = cpu_arpack_baseline(prob, last["iters"], max(int(last["r"]), 1),
+                                                      args.arpack_iters)
         if answers and args.workload != "snl":
             check_block = oracle_check(prob, args.workload, answers,
                                        {args.precision: last, **(prec or {})})
@@ -526,6 +531,47 @@ def cpu_baseline(prob, gpu_iters, iters):
         "sample": f"{iters} full-eig PDHG iteration(s) of the same n={prob.n} instance "
                   f"({per_it:.2f} s each, setup {t_setup:.1f} s excluded), times the GPU "
                   f"iteration count {gpu_iters}",
+    }
+
+
+def cpu_arpack_baseline(prob, gpu_iters, r, iters):
+    """The paper's own CPU design beside the oracle: the same PDHG iteration
+    with the truncated projection from ARPACK (scipy eigsh, the r algebraically
+    largest eigenpairs, warm-started with the previous leading Ritz vector),
+    timed for `iters` iterations and extrapolated to the GPU's iteration count.
+    Uses the oracle's operators; not the oracle itself (ARPACK tolerance)."""
+    import numpy as np
+    from scipy.sparse.linalg import eigsh
+    import oracle as O
+    log(f"cpu baseline (ARPACK-style, r={r}): {iters} iteration(s) at n={prob.n} ...")
+    ops = O.Operators(prob)
+    alpha = 0.95 / ops.norm()
+    C = ops.C()
+    n, m = prob.n, prob.m
+    X = np.zeros((n, n))
+    y = np.zeros(m + prob.p)
+    MX = ops.apply(X)
+    v0 = None
+    k = min(r, n - 1)
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        W = X - alpha * (C - ops.adjoint(y))
+        vals, vecs = eigsh(W, k=k, which="LA", v0=v0, tol=1e-6)
+        v0 = vecs[:, int(np.argmax(vals))]
+        lp = np.maximum(vals, 0.0)
+        Xn = (vecs * lp) @ vecs.T
+        MXn = ops.apply(Xn)
+        y_half = -y + alpha * (2.0 * MXn - MX)
+        y = -O.dual_resolvent(y_half, alpha, ops.rhs[:m], ops.rhs[m:])
+        X, MX = Xn, MXn
+    per_it = (time.perf_counter() - t0) / iters
+    log(f"cpu baseline (ARPACK-style): {per_it:.2f}s per iteration")
+    return {
+        "value": round(per_it * gpu_iters, 1),
+        "unit": "s (extrapolated time-to-1e-4)",
+        "kind": "ARPACK-style LR-PD-SDP (scipy eigsh 'LA', tol 1e-6, warm start)",
+        "sample": f"the first {iters} iteration(s) from X = 0 at r = {k} ({per_it:.2f} s each), "
+                  f"times the GPU iteration count {gpu_iters}",
     }
 
 

@@ -772,8 +772,10 @@ struct FinArgs {
 __device__ void finalize_iteration(const FinArgs& f, double* small, const DevProblem& dp,
                                    const double* y, const double* y_old, double* red);
 
+// The finalising workgroup's code would raise the register count to 98 (four
+// workgroups per CU); capped at five waves per SIMD, the LDS limit, without spills.
 template <typename OutT>
-__global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t ld, int n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_write_w(OutT* __restrict__ W, int64_t ld, int n,
                                                  const double* __restrict__ V, int ldv, int r,
                                                  double* __restrict__ small, int lam_off,
                                                  DevProblem dp, const double* __restrict__ y,
@@ -800,17 +802,32 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
   const int tile_id = I * T + J;
   const int a0 = I * TILE, b0 = J * TILE;
   const double* lam = small + lam_off;
+  // The tile's pattern items are fetched first and their values gathered
+  // while the factor rows load and the products run (one item per thread; a
+  // longer list is finished after the products): the chain tile range ->
+  // item -> value would otherwise stall every workgroup for three memory
+  // latencies between its products and its stores.
+  int p0 = 0, p1 = 0;
+  if (sparse) {
+    p0 = dp.tile_ptr[tile_id];
+    p1 = dp.tile_ptr[tile_id + 1];
+  }
+  int my_item = -1, my_e = 0;
+  if (sparse && p0 + (int)threadIdx.x < p1) {
+    my_item = dp.tile_item[p0 + threadIdx.x];
+    my_e = dp.tile_e[p0 + threadIdx.x];
+  }
   // factor columns after the last positive lambda add nothing to the tile
   r = last_positive(lam, r);
   const int nq = rank1 ? dp.n_r1 : 0;
   const int rr = r + nq;
   // LDS: first the scaled factor rows of the column block (64 x rr, odd row
-  // stride rr + 1, rr <= KMAX + MAX_R1), staged once for the four waves with
+  // stride, rr <= KMAX + MAX_R1), staged once for the four waves with
   // coalesced loads; then, in the same memory, the 64 x 64 output tile,
   // unpadded with its columns permuted per row (element (a, c) at column
   // c ^ a), so that both a row and a column of it are read without bank
   // conflicts and the block needs 32 KB (five workgroups per CU) at rr < 64.
-  const int LDVB = rr + 1;
+  const int LDVB = rr | 1;   // odd, >= rr (columns >= rr are never read)
   auto tix = [](int a, int c) { return a * TILE + (c ^ a); };
   double* sVb = sm;
   double* sT = sm;
@@ -820,6 +837,7 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
   // lane q of a wave holds column q (and q + 64) of a row: factor columns
   // scaled by lambda_q, then the rank-one terms scaled by
   // gamma_u = alpha sigma_u y_u
+  double my_val = 0.0;
   for (int half = 0; half < 2; ++half) {
     const int q = lane + 64 * half;
     if (half == 1 && rr <= 64) break;
@@ -833,13 +851,19 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
       uu = dp.r1_u + (int64_t)u * dp.npad;
     }
     if (q < LDVB) {
-      for (int row = w; row < TILE; row += 4) {
-        const int gb = b0 + row;
-        double v = 0.0;
-        if (q < r) v = V[(int64_t)gb * ldv + q] * sc;
-        else if (q < rr) v = uu[gb] * sc;
-        sVb[row * LDVB + q] = v;
+      double v[TILE / 4];
+#pragma unroll
+      for (int i = 0; i < TILE / 4; ++i) {
+        const int gb = b0 + w + 4 * i;
+        v[i] = 0.0;
+        if (q < r) v[i] = V[(int64_t)gb * ldv + q];
+        else if (q < rr) v[i] = uu[gb];
       }
+      if (half == 0 && my_item >= 0) my_val = dval[my_e];
+#pragma unroll
+      for (int i = 0; i < TILE / 4; ++i) sVb[(w + 4 * i) * LDVB + q] = v[i] * sc;
+    } else if (half == 0 && my_item >= 0) {
+      my_val = dval[my_e];
     }
   }
   __syncthreads();
@@ -883,8 +907,9 @@ __global__ __launch_bounds__(256) void k_write_w(OutT* __restrict__ W, int64_t l
   }
   if (sparse) {
     __syncthreads();
-    const int t0 = dp.tile_ptr[tile_id], t1 = dp.tile_ptr[tile_id + 1];
-    for (int t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+    // every item of the tile pair is a distinct (row, column) of the tile
+    if (my_item >= 0) sT[tix(my_item >> 8, my_item & 255)] += my_val;
+    for (int t = p0 + (int)blockDim.x + (int)threadIdx.x; t < p1; t += blockDim.x) {
       const int it = dp.tile_item[t];
       sT[tix(it >> 8, it & 255)] += dval[dp.tile_e[t]];
     }

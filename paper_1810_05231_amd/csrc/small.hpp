@@ -725,7 +725,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
     // target (it bounds the error of the factors), not to the last ulp; a
     // stagnating defect below 1e-12 is taken as converged as well.
     const double rtol = fmax(1e-13, 1e-3 * jac_tol);
-    double offR_prev = 1.0;
+    double offR_prev = 1.0, offS_prev = 1e308;
     int st = 0;
     for (;; ++st) {
       offR = sqrt(aR);
@@ -733,8 +733,13 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
       smax = fmax(mx, 1e-300);
       const bool rdone = offR <= rtol || (offR <= 1e-12 && offR > 0.25 * offR_prev);
       const bool conv = rdone && offS <= fmax(jac_tol, 1e-15) * smax;
-      if (conv || st == oa_steps || !(offR < 0.5) || !isfinite(offS) || !isfinite(smax)) break;
+      // couplings that no longer shrink (pairs too close for the Newton update)
+      // within the acceptance level are left to the Jacobi rotations
+      const bool stall = rdone && offS <= 1e-4 * smax && offS > 0.5 * offS_prev;
+      if (conv || stall || st == oa_steps || !(offR < 0.5) || !isfinite(offS) || !isfinite(smax))
+        break;
       offR_prev = offR;
+      offS_prev = offS;
       const double delta = 2.0 * (offS + smax * offR);
       RR_FOR_KK(t, i, j) {
         const double rij = ((i == j) ? 1.0 : 0.0) - Gc[i * ld + j];

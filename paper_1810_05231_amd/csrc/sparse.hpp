@@ -242,15 +242,38 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
   const int r = f.r, r0 = f.r_old;
   double x2 = 0.0, x01 = 0.0;
   const double* fr = small + SL::FR;   // slice sums formed by the dual-step kernel
-  for (int t = tid; t < r * r + r * r0; t += nt) {
-    const double g = fr[t];
-    if (t < r * r) {
-      const int a = t / r, b = t - (t / r) * r;
-      x2 += lam[a] * lam[b] * g * g;
-    } else {
-      const int e = t - r * r;
-      const int a = e / r0, b = e - (e / r0) * r0;
-      x01 += lam[a] * lam0[b] * g * g;
+  // both iterates' lambdas in LDS after the reduction scratch (`red` holds at
+  // least 32 KB); the factor Gram entries are loaded FB at a time per thread
+  double* lam_s = red + 16 * (9 + MAX_R1);
+  double* lam0_s = lam_s + KMAX;
+  for (int t = tid; t < 2 * KMAX; t += nt) {
+    if (t < KMAX) lam_s[t] = t < r ? lam[t] : 0.0;
+    else lam0_s[t - KMAX] = (t - KMAX < r0) ? lam0[t - KMAX] : 0.0;
+  }
+  __syncthreads();
+  {
+    constexpr int FB = 8;
+    const int nf = r * r + r * r0;
+    for (int t0 = tid; t0 < nf; t0 += FB * nt) {
+      double g[FB];
+#pragma unroll
+      for (int u = 0; u < FB; ++u) {
+        const int t = t0 + u * nt;
+        g[u] = t < nf ? fr[t] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < FB; ++u) {
+        const int t = t0 + u * nt;
+        if (t >= nf) continue;
+        if (t < r * r) {
+          const int a = t / r, b = t - (t / r) * r;
+          x2 += lam_s[a] * lam_s[b] * g[u] * g[u];
+        } else {
+          const int e = t - r * r;
+          const int a = e / r0, b = e - (e / r0) * r0;
+          x01 += lam_s[a] * lam0_s[b] * g[u] * g[u];
+        }
+      }
     }
   }
   double ed2 = 0.0, cross = 0.0, dobj = 0.0, bad = 0.0, ymx = 0.0;
@@ -266,7 +289,7 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     lo = fmin(lo, o[0]); mdy2 += o[1]; lo2 = fmin(lo2, o[2]);
     for (int q = 0; q < MAX_R1; ++q) cq[q] += o[4 + q];
   }
-  for (int t = tid; t < r; t += nt) lth += lam[t] * small[SL::THETA + t];
+  for (int t = tid; t < r; t += nt) lth += lam_s[t] * small[SL::THETA + t];
   {
     double v[9 + MAX_R1] = {x2, x01, ed2, cross, dobj, bad, ymx, lth, mdy2};
     for (int q = 0; q < MAX_R1; ++q) v[9 + q] = cq[q];

@@ -161,6 +161,8 @@ def _instance(kind, n, seed=7):
         return I.planted_lowrank(n, 48, seed)
     if kind == "mimo":
         return I.mimo(n - 1, seed)
+    if kind == "snl_noisy":
+        return I.snl(n - 2, seed=seed, noise=0.05)
     return I.snl(n - 2, seed=seed, noise=0.0)
 
 
@@ -171,7 +173,8 @@ def _instance(kind, n, seed=7):
                                         ("equip", 40, 2, 25), ("maxcut", 200, 4, 20),
                                         ("equip", 180, 3, 20), ("snl", 102, 4, 30),
                                         ("snl", 302, 8, 30), ("planted", 300, 48, 10),
-                                        ("planted", 300, 64, 10), ("mimo", 51, 4, 15)])
+                                        ("planted", 300, 64, 10), ("mimo", 51, 4, 15),
+                                        ("snl_noisy", 102, 4, 30)])
 def test_iterates_match_oracle(torch_cuda, kind, n, r, K):
     from paper_1810_05231_amd import Solver
     _say("iterates", kind, n, r, K)
@@ -443,6 +446,32 @@ def test_hyperplane_rounding_matches_oracle(torch_cuda):
 
 
 # ------------------------------------------------- sensor localisation
+def test_noisy_snl_dual_ray_certifies_an_empty_band_set(torch_cuda):
+    """5 % multiplicative distance noise with the +-10 % bands (the workload as
+    configured): the band set is empty.  The GPU's dual iterates run away along
+    a direction that is a Farkas certificate of that (checked exactly as for
+    the oracle's own run in test_oracle_snl_infeasible.py), and the solve never
+    reports convergence."""
+    from paper_1810_05231_amd import Solver
+    from snl_farkas import farkas_check, trace_bound
+    prob = I.snl(30, 1, noise=0.05)
+    K, L = 6000, 2000
+    s = Solver(prob, tol=1e-12, r0=prob.n, max_iters=K)   # the full projection, as the oracle's run
+    info1 = s.step(K - L)
+    _, y1 = s.solution(on_device=False)
+    info2 = s.step(L)
+    _, y2 = s.solution(on_device=False)
+    _say("  noisy snl", info1["status_name"], info2["status_name"], info2["iters"],
+         info2["rho_p"], info2["rho_d"])
+    assert info2["status_name"] != "converged" and info2["iters"] == K
+    ops = O.Operators(prob)
+    d = (y2 - y1) * ops.scale / L        # duals of the row-scaled problem
+    value, lam_max, ok = farkas_check(ops, d, trace_bound(prob))
+    _say("  farkas value", value, "lambda_max", lam_max)
+    assert value > 0.0 and ok
+    s.close()
+
+
 @pytest.mark.parametrize("sensors,precision,must_converge", [(60, 0, True), (100, 0, True),
                                                              (300, 0, False), (300, 1, False)])
 def test_snl_solve_feasible(torch_cuda, sensors, precision, must_converge):
