@@ -36,7 +36,11 @@ PEAK_FP64_TFLOPS = 78.6      # dense FP64 MFMA
 # WRITE_SIZE, calibrated against a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0); see profiles/k_block_partial_f64_k_write_w_n5000_k64_hbm_counters.md.
 # Must be re-measured whenever k_block_partial_f64 or its chunking changes.
-PASS_K64_TRAFFIC_BYTES = {"read": 227.8e6, "write": 23.3e6}
+PASS_K64_TRAFFIC_BYTES = {"read": 227.9e6, "write": 23.3e6}
+# the same counters for the dense write (tile pairs of W+) and the MFMA-busy
+# fraction (rocprofv3 MfmaUtil) of both kernels at k = 64
+WRITE_TRAFFIC_BYTES = {"read": 45.8e6, "write": 200.0e6}
+MFMA_UTIL = {"pass": 0.474, "write": 0.183}
 
 
 def log(*a):
@@ -229,9 +233,10 @@ def main():
     roofline.update({
         "traffic": (PASS_K64_TRAFFIC_BYTES["read"] + PASS_K64_TRAFFIC_BYTES["write"]
                     if (n == 5000 and args.workload == "maxcut" and args.precision == "fp64") else None),
-        "traffic_note": "HBM bytes per k=64 launch (read 227.8 MB + write 23.3 MB of split-K "
+        "traffic_note": "HBM bytes per k=64 launch (read 227.9 MB + write 23.3 MB of split-K "
                         "partials, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated) vs 204.5 MB "
                         "algorithmic read",
+        "mfma_util_counter": MFMA_UTIL["pass"] if n == 5000 else None,
         "kernel": "k_block_partial_f64 (dense pass W B, FP64 MFMA)",
         "launches": pass_cnt,
         "avg_launch_us": round(pass_s / max(pass_cnt, 1) * 1e6, 2),
@@ -242,7 +247,11 @@ def main():
         "write_kernel": {"name": "k_write_w", "launches": write_cnt,
                          "avg_launch_us": round(write_s / max(write_cnt, 1) * 1e6, 2),
                          "GBps": round(write_bytes / max(write_s, 1e-12) / 1e9, 1),
-                         "TFLOPs": round(write_flops / max(write_s, 1e-12) / 1e12, 2)},
+                         "TFLOPs": round(write_flops / max(write_s, 1e-12) / 1e12, 2),
+                         "traffic": (WRITE_TRAFFIC_BYTES["read"] + WRITE_TRAFFIC_BYTES["write"]
+                                     if (n == 5000 and args.workload == "maxcut"
+                                         and args.precision == "fp64") else None),
+                         "mfma_util_counter": MFMA_UTIL["write"] if n == 5000 else None},
         "sweep_share_of_solve": round((pass_s + write_s) / max(prof_wall, 1e-9), 3),
         "profiled_solve_s": round(prof_wall, 4),
     })

@@ -105,6 +105,14 @@ struct DevProblem {
   const double* row_w;    // scaled coefficient, x2 off the diagonal
   const int* sym_ptr;     // symmetric rows of the pattern (n + 1)
   const int* sym_e;
+  // per slot of sym_e: the entry's other index (the row itself on the diagonal),
+  // C value, row range [t0, t1) and first row / value (-1 / 0 if none)
+  const int* slot_other;
+  const int* slot_t0;
+  const int* slot_t1;
+  const int* slot_row0;
+  const double* slot_c;
+  const double* slot_val0;
   int tiles_side;         // npad / TILE
   const int* tile_ptr;    // full (mirrored) pattern bucketed by tile
   const int* tile_item;   // (local row << 8) | local col

@@ -675,10 +675,8 @@ __global__ __launch_bounds__(256) void k_implicit_rows(DevProblem dp, const doub
       int other = 0;
       double dv = 0.0;
       if (s < s1) {
-        const int e = dp.sym_e[s];
-        const int ea = dp.pat_a[e], eb = dp.pat_b[e];
-        other = (ea == i) ? eb : ea;
-        dv = dval[e];
+        other = dp.slot_other[s];
+        dv = dval[dp.sym_e[s]];
       }
       const int cnt = min(64, s1 - base);
 #pragma unroll 8

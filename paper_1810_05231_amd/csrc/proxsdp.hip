@@ -60,6 +60,8 @@ struct Host {
   std::vector<int> row_ptr, row_a, row_b;
   std::vector<double> row_w;
   std::vector<int> sym_ptr, sym_e;
+  std::vector<int> slot_other, slot_t0, slot_t1, slot_row0;
+  std::vector<double> slot_c, slot_val0;
   std::vector<int> tile_ptr, tile_item, tile_e;
   int n_r1 = 0;
   std::vector<int> r1_row;
@@ -370,6 +372,29 @@ int preprocess(const proxsdp_problem* pb, int row_scaling, Host& h) {
       if (h.pat_a[e] != h.pat_b[e]) h.sym_e[fill[h.pat_b[e]]++] = e;
     }
   }
+  // per-slot copies of what the pattern kernels read for an entry (its other
+  // index, C value, row range and first row), so that a row's slots are read
+  // contiguously instead of through the entry index
+  {
+    const size_t ns = h.sym_e.size();
+    h.slot_other.resize(ns);
+    h.slot_t0.resize(ns);
+    h.slot_t1.resize(ns);
+    h.slot_row0.resize(ns);
+    h.slot_c.resize(ns);
+    h.slot_val0.resize(ns);
+    for (int a = 0; a < n; ++a)
+      for (int sl = h.sym_ptr[a]; sl < h.sym_ptr[a + 1]; ++sl) {
+        const int e = h.sym_e[sl];
+        h.slot_other[sl] = (h.pat_a[e] == a) ? h.pat_b[e] : h.pat_a[e];
+        h.slot_c[sl] = h.pat_c[e];
+        h.slot_t0[sl] = h.pat_rptr[e];
+        h.slot_t1[sl] = h.pat_rptr[e + 1];
+        const bool any = h.pat_rptr[e + 1] > h.pat_rptr[e];
+        h.slot_row0[sl] = any ? h.pat_row[h.pat_rptr[e]] : -1;
+        h.slot_val0[sl] = any ? h.pat_val[h.pat_rptr[e]] : 0.0;
+      }
+  }
   // tile lists of the mirrored pattern
   const int ts = h.npad / TILE;
   h.tile_ptr.assign((size_t)ts * ts + 1, 0);
@@ -610,6 +635,12 @@ static size_t carve(proxsdp_handle* H, void* ws) {
   d.row_w = c.take<double>(h.row_w.size());
   d.sym_ptr = c.take<int>(h.sym_ptr.size());
   d.sym_e = c.take<int>(h.sym_e.size());
+  d.slot_other = c.take<int>(h.slot_other.size());
+  d.slot_t0 = c.take<int>(h.slot_t0.size());
+  d.slot_t1 = c.take<int>(h.slot_t1.size());
+  d.slot_row0 = c.take<int>(h.slot_row0.size());
+  d.slot_c = c.take<double>(h.slot_c.size());
+  d.slot_val0 = c.take<double>(h.slot_val0.size());
   d.tile_ptr = c.take<int>(h.tile_ptr.size());
   d.tile_item = c.take<int>(h.tile_item.size());
   d.tile_e = c.take<int>(h.tile_e.size());
@@ -1641,6 +1672,8 @@ int proxsdp_create(const proxsdp_problem* pb, const proxsdp_options* opt, void* 
   UP(d.pat_rptr, h.pat_rptr); UP(d.pat_row, h.pat_row); UP(d.pat_val, h.pat_val);
   UP(d.row_ptr, h.row_ptr); UP(d.row_a, h.row_a); UP(d.row_b, h.row_b); UP(d.row_w, h.row_w);
   UP(d.sym_ptr, h.sym_ptr); UP(d.sym_e, h.sym_e);
+  UP(d.slot_other, h.slot_other); UP(d.slot_t0, h.slot_t0); UP(d.slot_t1, h.slot_t1);
+  UP(d.slot_row0, h.slot_row0); UP(d.slot_c, h.slot_c); UP(d.slot_val0, h.slot_val0);
   UP(d.tile_ptr, h.tile_ptr); UP(d.tile_item, h.tile_item); UP(d.tile_e, h.tile_e);
   UP(d.r1_u, h.r1_u); UP(d.row_r1, h.row_r1); UP(d.rhs, h.rhs);
 #undef UP

@@ -181,30 +181,41 @@ __global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __
     double center = 0.0, radius = 0.0, center2 = 0.0, radius2 = 0.0;
     const int s0 = dp.sym_ptr[a], s1 = dp.sym_ptr[a + 1];
     for (int s = s0 + lane; s < s1; s += 64) {
+      // the slot's copies of its entry's data: one contiguous read per field
       const int e = dp.sym_e[s];
-      const int ea = dp.pat_a[e], eb = dp.pat_b[e];
+      const int other = dp.slot_other[s];
+      const int i0 = dp.slot_row0[s];
+      const int t1 = dp.slot_t1[s];
+      const double v0 = dp.slot_val0[s];
+      const double cv = dp.slot_c[s];
       double my = 0.0, md = 0.0;
-      for (int t = dp.pat_rptr[e]; t < dp.pat_rptr[e + 1]; ++t) {
-        const int i = dp.pat_row[t];
-        const double v = dp.pat_val[t];
-        const double yi = y[i];
-        my += alpha * yi * v;
-        md += (yi - y_old[i]) * v;
+      if (i0 >= 0) {
+        const double yi = y[i0];
+        my += alpha * yi * v0;
+        md += (yi - y_old[i0]) * v0;
+        for (int t = dp.slot_t0[s] + 1; t < t1; ++t) {
+          const int i = dp.pat_row[t];
+          const double v = dp.pat_val[t];
+          const double yt = y[i];
+          my += alpha * yt * v;
+          md += (yt - y_old[i]) * v;
+        }
       }
-      const double dv = -alpha * dp.pat_c[e] + my;
-      if (ea == eb) {
+      const double dv = -alpha * cv + my;
+      const bool diag = other == a;
+      if (diag) {
         center += dv;
         center2 += my;
       } else {
         radius += fabs(dv);
         radius2 += fabs(my);
       }
-      if (ea == a) {  // owner of the entry
+      if (a <= other) {  // owner of the entry (its smaller index)
         dval[e] = dv;
-        const double w = (ea == eb) ? 1.0 : 2.0;
+        const double w = diag ? 1.0 : 2.0;
         mdy2 += w * md * md;
         for (int q = 0; q < dp.n_r1; ++q)
-          crossq[q] += w * md * dp.r1_u[(int64_t)q * dp.npad + ea] * dp.r1_u[(int64_t)q * dp.npad + eb];
+          crossq[q] += w * md * dp.r1_u[(int64_t)q * dp.npad + a] * dp.r1_u[(int64_t)q * dp.npad + other];
       }
     }
     center = wave_sum(center);
@@ -276,18 +287,39 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
       }
     }
   }
+  // block partials of the dual step and of the pattern kernel, PB blocks per
+  // thread loaded before any is added
+  constexpr int PB = 4;
   double ed2 = 0.0, cross = 0.0, dobj = 0.0, bad = 0.0, ymx = 0.0;
-  for (int b = tid; b < f.nrow_blocks; b += nt) {
-    const double* o = f.row_part + (int64_t)b * ROW_PART;
-    ed2 += o[0]; cross += o[1]; dobj += o[2]; bad += o[3]; ymx += o[4];
+  for (int b0 = tid; b0 < f.nrow_blocks; b0 += PB * nt) {
+    double o[PB][ROW_PART];
+#pragma unroll
+    for (int u = 0; u < PB; ++u)
+#pragma unroll
+      for (int j = 0; j < ROW_PART; ++j)
+        o[u][j] = (b0 + u * nt < f.nrow_blocks) ? f.row_part[(int64_t)(b0 + u * nt) * ROW_PART + j] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      ed2 += o[u][0]; cross += o[u][1]; dobj += o[u][2]; bad += o[u][3]; ymx += o[u][4];
+    }
   }
   double lo = 1e308, lo2 = 1e308, mdy2 = 0.0, lth = 0.0;
   double cq[MAX_R1];
   for (int q = 0; q < MAX_R1; ++q) cq[q] = 0.0;
-  for (int b = tid; b < f.npat_blocks; b += nt) {
-    const double* o = f.pat_part + (int64_t)b * PAT_PART;
-    lo = fmin(lo, o[0]); mdy2 += o[1]; lo2 = fmin(lo2, o[2]);
-    for (int q = 0; q < MAX_R1; ++q) cq[q] += o[4 + q];
+  for (int b0 = tid; b0 < f.npat_blocks; b0 += PB * nt) {
+    double o[PB][PAT_PART];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const bool in = b0 + u * nt < f.npat_blocks;
+#pragma unroll
+      for (int j = 0; j < PAT_PART; ++j)
+        o[u][j] = in ? f.pat_part[(int64_t)(b0 + u * nt) * PAT_PART + j] : ((j == 0 || j == 2) ? 1e308 : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      lo = fmin(lo, o[u][0]); mdy2 += o[u][1]; lo2 = fmin(lo2, o[u][2]);
+      for (int q = 0; q < MAX_R1; ++q) cq[q] += o[u][4 + q];
+    }
   }
   for (int t = tid; t < r; t += nt) lth += lam_s[t] * small[SL::THETA + t];
   {
