@@ -432,6 +432,35 @@ __device__ __forceinline__ void strip_mm(double* Out, int ldo, const double* X, 
   }
 }
 
+// For every entry (i, j) of a k x k matrix, load(i, j, v) fills NV values
+// (global loads) and store(i, j, v) consumes them; each thread issues the
+// loads of four entries before it stores any, so a copy from global memory
+// into LDS waits for memory once per four entries instead of once per entry.
+template <int NV, class LoadF, class StoreF>
+__device__ __forceinline__ void kk_batched(int k, LoadF load, StoreF store) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int kk = k * k;
+  for (int t0 = tid; t0 < kk; t0 += 4 * nt) {
+    double v[4][NV];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * nt;
+      if (t < kk) {
+        const int i = t / k, j = t - (t / k) * k;
+        load(i, j, v[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * nt;
+      if (t < kk) {
+        const int i = t / k, j = t - (t / k) * k;
+        store(i, j, v[u]);
+      }
+    }
+  }
+}
+
 // Threads of k_small_rr (eight waves; the Newton step below assumes it).
 constexpr int RR_THREADS = 512;
 
@@ -678,11 +707,18 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
     double* Sc = B1;
     double* F = B2;
     double* Xc = B3;   // accumulated coefficients X (G-orthonormalising, diagonalising)
-    RR_FOR_KK(t, i, j) {
-      Gc[i * ld + j] = 0.5 * (G[i * k + j] + G[j * k + i]) * d[i] * d[j];
-      Sc[i * ld + j] = 0.5 * (T[i * k + j] + T[j * k + i]) * d[i] * d[j];
-      Xc[i * ld + j] = (i == j) ? 1.0 : 0.0;
-    }
+    kk_batched<4>(k,
+        [&](int i, int j, double* v) {
+          v[0] = G[i * k + j];
+          v[1] = G[j * k + i];
+          v[2] = T[i * k + j];
+          v[3] = T[j * k + i];
+        },
+        [&](int i, int j, const double* v) {
+          Gc[i * ld + j] = 0.5 * (v[0] + v[1]) * d[i] * d[j];
+          Sc[i * ld + j] = 0.5 * (v[2] + v[3]) * d[i] * d[j];
+          Xc[i * ld + j] = (i == j) ? 1.0 : 0.0;
+        });
     __syncthreads();
     double offR = 1.0, offS = 1.0, smax = 1.0;
     // important pairs: those touching a positive value among the r largest.
@@ -803,12 +839,19 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
     double* L = B0;
     double* M = B1;
     double* U = B2;
-    RR_FOR_KK(t, i, j) {
-      const double tij = 0.5 * (T[i * k + j] + T[j * k + i]);
-      const double gij = 0.5 * (G[i * k + j] + G[j * k + i]);
-      L[i * ld + j] = gij * d[i] * d[j] + ((i == j) ? 1e-15 * k : 0.0);
-      M[i * ld + j] = tij * d[i] * d[j];
-    }
+    kk_batched<4>(k,
+        [&](int i, int j, double* v) {
+          v[0] = G[i * k + j];
+          v[1] = G[j * k + i];
+          v[2] = T[i * k + j];
+          v[3] = T[j * k + i];
+        },
+        [&](int i, int j, const double* v) {
+          const double tij = 0.5 * (v[2] + v[3]);
+          const double gij = 0.5 * (v[0] + v[1]);
+          L[i * ld + j] = gij * d[i] * d[j] + ((i == j) ? 1e-15 * k : 0.0);
+          M[i * ld + j] = tij * d[i] * d[j];
+        });
     __syncthreads();
     // Cholesky of the equilibrated G (lower, in L).  A column whose pivot
     // falls below 1e-14 (numerically dependent on the previous ones) is
@@ -918,10 +961,15 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
     Ybuf = L;
   }
   // coefficients out; P into Pbuf for the residual product
-  RR_FOR_KK(t, i, c) {
-    Sg[i * KMAX + c] = Sbuf[i * ld + c];
-    Pbuf[i * ld + c] = 0.5 * (P[i * k + c] + P[c * k + i]);
-  }
+  kk_batched<2>(k,
+      [&](int i, int c, double* v) {
+        v[0] = P[i * k + c];
+        v[1] = P[c * k + i];
+      },
+      [&](int i, int c, const double* v) {
+        Sg[i * KMAX + c] = Sbuf[i * ld + c];
+        Pbuf[i * ld + c] = 0.5 * (v[0] + v[1]);
+      });
   __syncthreads();
   // Y = P S (MFMA), then s_c^T P s_c = ||W v_c||^2.
   lds_mm(Ybuf, ld, Pbuf, ld, false, Sbuf, ld, k);
