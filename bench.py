@@ -255,6 +255,10 @@ def main():
         "sweep_share_of_solve": round((pass_s + write_s) / max(prof_wall, 1e-9), 3),
         "profiled_solve_s": round(prof_wall, 4),
     })
+    if pass_cnt == 0:
+        roofline["note"] = ("no dense FP64 pass runs in this form (every pass applies W through its "
+                            "low-rank + sparse structure); its kernel times are in "
+                            "profiles/maxcut_n5000_implicit_solve_kernel_trace.md")
     # the projection sweep (dense passes + dense writes): algorithmic bytes of
     # the stored layout, and of the unique entries n(n+1)/2 of the symmetric W
     # and W+ (what a triangle-only layout would have to move), over the summed
