@@ -87,6 +87,8 @@ def main():
                     help="also run this many requests of the serving stream (the stream's first "
                          "requests; 512 is the whole stream)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serving-check-every", type=int, default=0,
+                    help="serving: iterations per control check (0 = library default)")
     ap.add_argument("--serving-precision", choices=["fp32", "implicit"], default="fp32",
                     help="form of the served solves")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
@@ -362,6 +364,8 @@ def serving_bench(args, dev):
     N = args.serving or 512
     code = {"fp32": 1, "implicit": 3}[args.serving_precision]
     opts = dict(precision=code, tol=args.tol, graphs=1)
+    if args.serving_check_every:
+        opts["check_every"] = args.serving_check_every
     srv = Server(device=dev, budget_bytes=int(args.budget_gib * (1 << 30)), max_slots=args.slots,
                  **opts)
     Ns = min(N, args.serving_sat) if args.serving_sat > 0 else N
@@ -391,6 +395,7 @@ def serving_bench(args, dev):
                     + {"fp32": "FP32 precision form", "implicit": "implicit FP64 form"}[args.serving_precision]
                     + ", Poisson arrivals",
         "slots": args.slots, "budget_GiB": args.budget_gib,
+        "check_every": args.serving_check_every or 10,
         "saturated_solves_per_s": round(thr, 3), "saturated_makespan_s": round(makespan, 3),
         "saturation_requests": Ns, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
         "arrival_rate_per_s": round(rate, 3),
