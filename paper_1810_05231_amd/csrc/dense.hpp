@@ -610,14 +610,18 @@ __global__ __launch_bounds__(256) void k_vtb(const double* __restrict__ V, int r
 // Slice sums of the V^T B and u^T B partials, scaled for the apply:
 //   small[VB + t KMAX + c]          = lambda_t (V^T B)_tc          (t < r)
 //   small[VB + KMAX^2 + q KMAX + c] = gamma_q (u_q^T B)_c,  gamma_q = alpha sigma_q y_row(q)
+// SVB_LANES lanes per value, each summing every SVB_LANES-th slice with the
+// loads of a batch in flight together, combined by a fixed butterfly.
+constexpr int SVB_LANES = 8, SVB_BATCH = 10;
 __global__ __launch_bounds__(256) void k_sum_vb(const double* __restrict__ vb_part, int nslices,
                                                 int r, int k, DevProblem dp,
                                                 const double* __restrict__ y, int lam_off,
                                                 double* __restrict__ small) {
   r = last_positive(small + lam_off, r);
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = g / SVB_LANES, part = g % SVB_LANES;
   const int n1 = r * k;
-  if (t >= n1 + dp.n_r1 * k) return;
+  if (t >= n1 + dp.n_r1 * k) return;   // whole groups of SVB_LANES lanes
   int src;
   double sc;
   if (t < n1) {
@@ -630,9 +634,19 @@ __global__ __launch_bounds__(256) void k_sum_vb(const double* __restrict__ vb_pa
     sc = small[SL::SC + S_ALPHA] * dp.r1_sigma[q] * y[dp.r1_row[q]];
   }
   double acc = 0.0;
-#pragma unroll 8
-  for (int s = 0; s < nslices; ++s) acc += vb_part[(int64_t)s * VB_STRIDE + src];
-  small[SL::VB + src] = sc * acc;
+  for (int s0 = part; s0 < nslices; s0 += SVB_LANES * SVB_BATCH) {
+    double v[SVB_BATCH];
+#pragma unroll
+    for (int u = 0; u < SVB_BATCH; ++u) {
+      const int s = s0 + u * SVB_LANES;
+      v[u] = s < nslices ? vb_part[(int64_t)s * VB_STRIDE + src] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < SVB_BATCH; ++u) acc += v[u];
+  }
+#pragma unroll
+  for (int o = 1; o < SVB_LANES; o <<= 1) acc += __shfl_xor(acc, o);
+  if (part == 0) small[SL::VB + src] = sc * acc;
 }
 
 // Z = W B applied exactly (rows of the precision form's Rayleigh-Ritz pass):
@@ -655,16 +669,26 @@ __global__ __launch_bounds__(256) void k_implicit_rows(DevProblem dp, const doub
   if (i < dp.n) {
     if (c < k) {
       const double* M = small + SL::VB;
-      const double* vrow = V + (int64_t)i * KMAX;
+      // the row of V in one coalesced load, its entries broadcast from lanes;
+      // the rows of M loaded 16 at a time before they are used
+      const double vv = V[(int64_t)i * KMAX + c];
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int t = 0;
-      for (; t + 3 < r; t += 4) {
-        a0 += vrow[t] * M[t * KMAX + c];
-        a1 += vrow[t + 1] * M[(t + 1) * KMAX + c];
-        a2 += vrow[t + 2] * M[(t + 2) * KMAX + c];
-        a3 += vrow[t + 3] * M[(t + 3) * KMAX + c];
+      for (int t0 = 0; t0 < r; t0 += 16) {
+        double mv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) mv[u] = (t0 + u < r) ? M[(t0 + u) * KMAX + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; u += 4) {
+          const double x0 = (t0 + u < r) ? __shfl(vv, t0 + u) : 0.0;
+          const double x1 = (t0 + u + 1 < r) ? __shfl(vv, t0 + u + 1) : 0.0;
+          const double x2 = (t0 + u + 2 < r) ? __shfl(vv, t0 + u + 2) : 0.0;
+          const double x3 = (t0 + u + 3 < r) ? __shfl(vv, t0 + u + 3) : 0.0;
+          a0 += x0 * mv[u];
+          a1 += x1 * mv[u + 1];
+          a2 += x2 * mv[u + 2];
+          a3 += x3 * mv[u + 3];
+        }
       }
-      for (; t < r; ++t) a0 += vrow[t] * M[t * KMAX + c];
       acc = (a0 + a1) + (a2 + a3);
       for (int q = 0; q < dp.n_r1; ++q)
         acc += dp.r1_u[(int64_t)q * dp.npad + i] * M[KMAX * KMAX + q * KMAX + c];

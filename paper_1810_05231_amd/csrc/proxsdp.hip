@@ -830,6 +830,7 @@ static void launch_write(proxsdp_handle* H, void* Wout, int out_prec, int64_t ld
   const size_t lds = (size_t)TILE * std::max(rr + 1, TILE) * sizeof(double);
   FinArgs f{};
   if (fin) f = *fin;
+  if (!tiles && !fin) return;
   const dim3 grid((tiles ? ts * (ts + 1) / 2 : 0) + (fin ? 1 : 0));
 #define WR(T)                                                                                   \
   hipLaunchKernelGGL(k_write_w<T>, grid, dim3(256), lds, H->st, static_cast<T*>(Wout), ld, H->n, \
@@ -887,7 +888,7 @@ static void launch_implicit(proxsdp_handle* H, const double* B, double* Z, bool 
                      k, H->dp.n_r1, H->dp.r1_u, H->npad, H->vb_part);
   const int cnt = (r + H->dp.n_r1) * k;
   if (cnt > 0)
-    hipLaunchKernelGGL(k_sum_vb, dim3((cnt + 255) / 256), dim3(256), 0, st, H->vb_part, H->nsl, r,
+    hipLaunchKernelGGL(k_sum_vb, dim3((SVB_LANES * cnt + 255) / 256), dim3(256), 0, st, H->vb_part, H->nsl, r,
                        k, H->dp, H->y, lam_slot(pp), H->small);
   hipLaunchKernelGGL(k_implicit_rows, dim3(H->npad / 4), dim3(256), 0, st, H->dp, H->V[pp], r,
                      lam_slot(pp), H->small, H->dval, B, k, Z);

@@ -1163,8 +1163,15 @@ __global__ void k_reduce_res(const double* __restrict__ fac_part, int nslices, i
   double worst = 0.0;
   const double scale = fmax(small[SL::SC + S_NORMW], 1e-300);
   const double* theta = small + SL::THETA;
-  int npos = 0;
-  while (npos < r && theta[npos] > 0.0) ++npos;
+  // leading positive values (one ballot of the first wave, shared through LDS)
+  __shared__ int npos_s;
+  if (threadIdx.x < 64) {
+    const int ln = threadIdx.x;
+    const unsigned long long stop = __ballot(ln < r && !(theta[ln < r ? ln : 0] > 0.0));
+    if (ln == 0) npos_s = stop ? (__ffsll((long long)stop) - 1) : r;
+  }
+  __syncthreads();
+  const int npos = npos_s;
   const int nchk = npos > 0 ? npos : (r > 0 ? 1 : 0);
   for (int c = threadIdx.x; c < r; c += blockDim.x) {
     double acc = 0.0;

@@ -236,6 +236,14 @@ __global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __
   }
 }
 
+// Number of leading positive values of v[0 .. r) (r <= 64), from one ballot
+// of the wave (every wave of the caller computes it).
+__device__ inline int leading_positive(const double* v, int r) {
+  const int ln = threadIdx.x & 63;
+  const unsigned long long stop = __ballot(ln < r && !(v[ln < r ? ln : 0] > 0.0));
+  return stop ? (__ffsll((long long)stop) - 1) : r;
+}
+
 // Runs in one workgroup (the extra block of the dense write).
 //   ||X+ - X||^2 = ||X+||^2 + ||X||^2 - 2 <X+, X> from the factor Grams,
 //   eps_p^2 = ||dX||^2 / alpha^2 + (2/alpha) <M(dX), dy> + ||M*(dy)||^2,
@@ -336,9 +344,7 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
   double worst = 0.0;
   {
     const double scale = fmax(small[SL::SC + S_NORMW], 1e-300);
-    const double* theta = small + SL::THETA;
-    int npos = 0;
-    while (npos < r && theta[npos] > 0.0) ++npos;
+    const int npos = leading_positive(small + SL::THETA, r);
     const int nchk = npos > 0 ? npos : (r > 0 ? 1 : 0);
     for (int c = tid; c < nchk; c += nt) worst = fmax(worst, sqrt(fr[FAC_RES + c]) / scale);
     for (int o = 32; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o));
@@ -349,10 +355,14 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     for (int w = 0; w < nw; ++w) worst = fmax(worst, red[w]);
   }
   if (tid == 0) {
-    small[SL::SC + S_MAXRES] = worst;
     double* sc = small + SL::SC;
+    // every scalar this tail reads, loaded before its first store
     const double alpha = sc[S_ALPHA];
     const double x2old = sc[f.x2_old];
+    const double lam_r = sc[S_LAMR], lam_r1 = sc[S_LAMR1], normw = sc[S_NORMW];
+    const double npos_rr = sc[S_NPOS], filt_x1 = sc[S_FILTX1], nonfinite = sc[S_NONFINITE];
+    const double iter = sc[S_ITER];
+    sc[S_MAXRES] = worst;
     const double dx2 = fmax(x2 + x2old - 2.0 * x01, 0.0);
     // rank-one part of M*(dy)
     double my2 = mdy2;
@@ -382,25 +392,27 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     // lambda_max(C) <= ||C||_F and Gershgorin of alpha M*(y) -- the second is
     // far tighter for a dense C
     sc[S_GERSH] = fmax(lo, -alpha * dp.norm_c + lo2) + gamma_lo;
-    if (bad > 0.0) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 3.0);
-    if (!isfinite(eps_p) || !isfinite(eps_d)) sc[S_NONFINITE] = fmax(sc[S_NONFINITE], 4.0);
+    double nf = nonfinite;
+    if (bad > 0.0) nf = fmax(nf, 3.0);
+    if (!isfinite(eps_p) || !isfinite(eps_d)) nf = fmax(nf, 4.0);
+    if (nf != nonfinite) sc[S_NONFINITE] = nf;
     IterRecord rec;
     rec.eps_p = eps_p;
     rec.eps_d = eps_d;
     rec.obj = obj;
     rec.dual_obj = dobj;
-    rec.lambda_r = sc[S_LAMR];
-    rec.lambda_r1 = sc[S_LAMR1];
-    rec.maxres = sc[S_MAXRES];
-    rec.normw = sc[S_NORMW];
-    rec.npos = sc[S_NPOS];
-    rec.filt_x1 = sc[S_FILTX1];
+    rec.lambda_r = lam_r;
+    rec.lambda_r1 = lam_r1;
+    rec.maxres = worst;
+    rec.normw = normw;
+    rec.npos = npos_rr;
+    rec.filt_x1 = filt_x1;
     // ring slot: given (set-up record) or the device iteration counter, so
     // that a captured round of iterations can be replayed
     int slot = f.ring_slot;
     if (slot < 0) {
-      slot = (int)sc[S_ITER] % RING;
-      sc[S_ITER] += 1.0;
+      slot = (int)iter % RING;
+      sc[S_ITER] = iter + 1.0;
     }
     f.ring[slot] = rec;
   }
