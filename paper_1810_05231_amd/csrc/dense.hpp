@@ -287,7 +287,7 @@ __global__ __launch_bounds__(512) void k_reduce_gram(const double* __restrict__ 
   // of all of a thread's pairs are loaded RG_BATCH chunks at a time before any
   // is added (one memory latency per batch, not per pair), and each element is
   // summed in chunk order
-  constexpr int RG_PAIRS = SLICE * KMAX / 2 / 512, RG_BATCH = 4;
+  constexpr int RG_PAIRS = SLICE * KMAX / 2 / 512, RG_BATCH = 5;
   int tt[RG_PAIRS];
   double2 z[RG_PAIRS], b[RG_PAIRS], bp[RG_PAIRS];
 #pragma unroll

@@ -1058,7 +1058,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(double* __restrict__ sm
 // slots of `small`: SG_LANES lanes per entry, each summing every SG_LANES-th
 // slice with SG_BATCH loads in flight, combined by a fixed butterfly (fixed
 // summation order).
-constexpr int SG_LANES = 8, SG_BATCH = 8;
+constexpr int SG_LANES = 8, SG_BATCH = 10;
 __global__ __launch_bounds__(256) void k_sum_grams(const double* __restrict__ gram_part,
                                                    int nslices, int k, double* __restrict__ small) {
   const int kk = k * k;

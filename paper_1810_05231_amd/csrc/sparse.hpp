@@ -51,6 +51,28 @@ __device__ inline void block_sum_many(double* v, double* red) {
   }
 }
 
+// Minima of two values over the workgroup with one pair of barriers.
+__device__ inline void block_min2(double& a, double& b, double* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a = fmin(a, __shfl_xor(a, o));
+    b = fmin(b, __shfl_xor(b, o));
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    red[2 * wave] = a;
+    red[2 * wave + 1] = b;
+  }
+  __syncthreads();
+  a = 1e308;
+  b = 1e308;
+  for (int w = 0; w < nw; ++w) {
+    a = fmin(a, red[2 * w]);
+    b = fmin(b, red[2 * w + 1]);
+  }
+}
+
 __device__ inline double block_min(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -72,7 +94,7 @@ __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double
                                                      double* __restrict__ MX,
                                                      double* __restrict__ MX_old,
                                                      double* __restrict__ row_part) {
-  __shared__ double red[16];
+  __shared__ double red[16 * (1 + MAX_R1)];
   // reduce the factor partials over the slices for the finalisation:
   // [V^T V (r x r) | V^T Vold (r x r_old)] -> small[FR ..], residuals -> small[FR + FAC_RES ..]
   // (FR_LANES lanes per value, each summing every FR_LANES-th slice with
@@ -108,6 +130,11 @@ __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double
   const int i = blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / ROW_LANES;
   double ed2 = 0.0, cross = 0.0, dobj = 0.0, bad = 0.0, ymx = 0.0;
   double mx = 0.0;
+  // the row's old values, loaded with its entries
+  const bool row_in = i < dp.rows;
+  const double mx0 = row_in ? MX[i] : 0.0;
+  const double y0 = row_in ? y[i] : 0.0;
+  const double rhs_i = row_in ? dp.rhs[i] : 0.0;
   if (i < dp.rows) {
     for (int e = dp.row_ptr[i]; e < dp.row_ptr[i + 1]; ++e) {
       const double* va = V + (int64_t)dp.row_a[e] * KMAX;
@@ -131,15 +158,13 @@ __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double
   }
   for (int o = ROW_LANES / 2; o > 0; o >>= 1) mx += __shfl_xor(mx, o);
   if (i < dp.rows && sub == 0) {
-    const double mx0 = MX[i];
-    const double y0 = y[i];
-    double u = y0 + alpha * (dp.rhs[i] - (2.0 * mx - mx0));
+    double u = y0 + alpha * (rhs_i - (2.0 * mx - mx0));
     if (i >= dp.m) u = fmin(u, 0.0);
     const double dy = u - y0, dmx = mx - mx0;
     const double rd = dy / alpha + dmx;
     ed2 = rd * rd;
     cross = dmx * dy;
-    dobj = dp.rhs[i] * u;
+    dobj = rhs_i * u;
     ymx = y0 * mx;   // <y, M(X+)> with the y that built the projected matrix
     if (!isfinite(u) || !isfinite(mx)) bad = 1.0;
     y_old[i] = y0;
@@ -147,11 +172,11 @@ __global__ __launch_bounds__(256) void k_gather_dual(DevProblem dp, const double
     MX_old[i] = mx0;
     MX[i] = mx;
   }
-  ed2 = block_sum(ed2, red);
-  cross = block_sum(cross, red);
-  dobj = block_sum(dobj, red);
-  bad = block_sum(bad, red);
-  ymx = block_sum(ymx, red);
+  {
+    double v[5] = {ed2, cross, dobj, bad, ymx};
+    block_sum_many<5>(v, red);
+    ed2 = v[0]; cross = v[1]; dobj = v[2]; bad = v[3]; ymx = v[4];
+  }
   if (threadIdx.x == 0) {
     double* o = row_part + (int64_t)blockIdx.x * ROW_PART;
     o[0] = ed2; o[1] = cross; o[2] = dobj; o[3] = bad; o[4] = ymx;
@@ -170,7 +195,7 @@ __global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __
                                                  const double* __restrict__ small,
                                                  double* __restrict__ dval,
                                                  double* __restrict__ pat_part) {
-  __shared__ double red[16];
+  __shared__ double red[16 * (1 + MAX_R1)];
   const double alpha = small[SL::SC + S_ALPHA];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -225,10 +250,15 @@ __global__ __launch_bounds__(256) void k_pattern(DevProblem dp, const double* __
     lo = fmin(lo, center - radius);
     lo2 = fmin(lo2, center2 - radius2);
   }
-  lo = block_min(lo, red);
-  lo2 = block_min(lo2, red);
-  mdy2 = block_sum(mdy2, red);
-  for (int q = 0; q < MAX_R1; ++q) crossq[q] = block_sum(crossq[q], red);
+  block_min2(lo, lo2, red);
+  {
+    double v[1 + MAX_R1];
+    v[0] = mdy2;
+    for (int q = 0; q < MAX_R1; ++q) v[1 + q] = crossq[q];
+    block_sum_many<1 + MAX_R1>(v, red);
+    mdy2 = v[0];
+    for (int q = 0; q < MAX_R1; ++q) crossq[q] = v[1 + q];
+  }
   if (threadIdx.x == 0) {
     double* o = pat_part + (int64_t)blockIdx.x * PAT_PART;
     o[0] = lo; o[1] = mdy2; o[2] = lo2; o[3] = 0.0;
@@ -338,8 +368,7 @@ __device__ void finalize_iteration(const FinArgs& f, double* small, const DevPro
     ymx = v[6]; lth = v[7]; mdy2 = v[8];
     for (int q = 0; q < MAX_R1; ++q) cq[q] = v[9 + q];
   }
-  lo = block_min(lo, red);
-  lo2 = block_min(lo2, red);
+  block_min2(lo, lo2, red);
   // true Ritz residuals of the kept pairs (row-wise partials of the final round)
   double worst = 0.0;
   {
