@@ -36,11 +36,11 @@ PEAK_FP64_TFLOPS = 78.6      # dense FP64 MFMA
 # WRITE_SIZE, calibrated against a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0); see profiles/k_block_partial_f64_k_write_w_n5000_k64_hbm_counters.md.
 # Must be re-measured whenever k_block_partial_f64 or its chunking changes.
-PASS_K64_TRAFFIC_BYTES = {"read": 227.9e6, "write": 23.3e6}
+PASS_K64_TRAFFIC_BYTES = {"read": 228.1e6, "write": 23.3e6}
 # the same counters for the dense write (tile pairs of W+) and the MFMA-busy
 # fraction (rocprofv3 MfmaUtil) of both kernels at k = 64
 WRITE_TRAFFIC_BYTES = {"read": 45.8e6, "write": 200.0e6}
-MFMA_UTIL = {"pass": 0.474, "write": 0.183}
+MFMA_UTIL = {"pass": 0.522, "write": 0.177}
 
 
 def log(*a):
@@ -234,10 +234,14 @@ def main():
     roofline = dict(roof)
     roofline.update({
         "traffic": (PASS_K64_TRAFFIC_BYTES["read"] + PASS_K64_TRAFFIC_BYTES["write"]
-                    if (n == 5000 and args.workload == "maxcut" and args.precision == "fp64") else None),
-        "traffic_note": "HBM bytes per k=64 launch (read 227.9 MB + write 23.3 MB of split-K "
-                        "partials, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated) vs 204.5 MB "
-                        "algorithmic read",
+                    if (PASS_K64_TRAFFIC_BYTES and n == 5000 and args.workload == "maxcut"
+                        and args.precision == "fp64") else None),
+        "traffic_note": ("HBM bytes per k=64 launch (read %.1f MB + write %.1f MB of split-K "
+                         "partials, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated) vs 204.5 MB "
+                         "algorithmic read" % (PASS_K64_TRAFFIC_BYTES["read"] / 1e6,
+                                               PASS_K64_TRAFFIC_BYTES["write"] / 1e6)
+                         if PASS_K64_TRAFFIC_BYTES else
+                         "counters not taken for the current pass kernel"),
         "mfma_util_counter": MFMA_UTIL["pass"] if n == 5000 else None,
         "kernel": "k_block_partial_f64 (dense pass W B, FP64 MFMA)",
         "launches": pass_cnt,
