@@ -774,7 +774,7 @@ static void launch_reduce(const double* part, int nchunks, double* Z, const doub
                           double cc, double ce, bool grams, hipStream_t st,
                           const double* filt = nullptr) {
   const size_t lds = 2 * (size_t)SLICE * k * sizeof(double);
-  hipLaunchKernelGGL(k_reduce_gram, dim3(n_slices(npad)), dim3(512), lds, st, part, nchunks, Z, B,
+  hipLaunchKernelGGL(k_reduce_gram, dim3(n_slices(npad)), dim3(1024), lds, st, part, nchunks, Z, B,
                      Bprev, npad, k, gram_part, cheb, cc, ce, grams ? 1 : 0, filt);
 }
 
