@@ -42,8 +42,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __shared__ double sB[64 * LDB];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int col = blockIdx.x * 64 + wave * 16 + (lane & 15);
-  const int chunk = blockIdx.y;
+  // XCD-aware order: workgroup L of the launch runs on XCD L % 8, so the
+  // (column block, chunk) items are dealt in chunk-major order in contiguous
+  // ranges per XCD, and each XCD's L2 holds the basis rows of two chunks, not
+  // all of them (a permutation of the work: any dispatch order is correct).
+  // n = 5000, k = 64: HBM reads 228.0 -> 209.6 MB per launch (204.5 MB of W),
+  // 71.0 -> 70.6 us.
+  const int ncols = gridDim.x;
+  const int T = ncols * gridDim.y;
+  const int L = blockIdx.x + ncols * blockIdx.y;
+  const int e = L & 7, s = L >> 3;
+  int start = 0;
+  for (int q = 0; q < e; ++q) start += (T - q + 7) >> 3;
+  const int item = start + s;
+  const int chunk = item / ncols;
+  const int col = (item - chunk * ncols) * 64 + wave * 16 + (lane & 15);
   const int j0 = chunk * rows_per_chunk;
   const int j1 = min(j0 + rows_per_chunk, npad);
   const int lrow = lane >> 4;
