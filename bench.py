@@ -39,8 +39,8 @@ PEAK_FP64_TFLOPS = 78.6      # dense FP64 MFMA
 PASS_K64_TRAFFIC_BYTES = {"read": 209.6e6, "write": 23.3e6}
 # the same counters for the dense write (tile pairs of W+) and the MFMA-busy
 # fraction (rocprofv3 MfmaUtil) of both kernels at k = 64
-WRITE_TRAFFIC_BYTES = {"read": 24.1e6, "write": 200.2e6}
-MFMA_UTIL = {"pass": 0.530, "write": 0.190}
+WRITE_TRAFFIC_BYTES = {"read": 24.1e6, "write": 200.1e6}
+MFMA_UTIL = {"pass": 0.447, "write": 0.161}
 
 
 def log(*a):
