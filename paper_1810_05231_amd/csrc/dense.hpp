@@ -63,22 +63,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   d4 acc[KB];
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) acc[kb] = d4{0.0, 0.0, 0.0, 0.0};
+  // entry (row, col) of W, zero outside n x n when W is not padded
+  auto w_at = [&](int row) -> double {
+    if (PADDED) return W[(int64_t)row * ld + col];
+    return (row < n && col < n) ? W[(int64_t)row * ld + col] : 0.0;
+  };
   double w[16];
   typedef double dd2 __attribute__((ext_vector_type(2)));
   dd2 bq[NQ];
-#define LOAD_STEP(jj)                                                              \
-  {                                                                                \
-    _Pragma("unroll") for (int u = 0; u < 16; ++u) {                               \
-      const int row = (jj) + 4 * u + lrow;                                         \
-      if (PADDED)                                                                  \
-        w[u] = W[(int64_t)row * ld + col];                                         \
-      else                                                                         \
-        w[u] = (row < n && col < n) ? W[(int64_t)row * ld + col] : 0.0;            \
-    }                                                                              \
-    const dd2* src = reinterpret_cast<const dd2*>(B + (int64_t)(jj) * ldk);       \
-    _Pragma("unroll") for (int x = 0; x < NQ; ++x) bq[x] = src[threadIdx.x + 256 * x]; \
+  if (j0 < j1) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) w[u] = w_at(j0 + 4 * u + lrow);
+    const dd2* src = reinterpret_cast<const dd2*>(B + (int64_t)j0 * ldk);
+#pragma unroll
+    for (int x = 0; x < NQ; ++x) bq[x] = src[threadIdx.x + 256 * x];
   }
-  if (j0 < j1) LOAD_STEP(j0);
   for (int j = j0; j < j1; j += 64) {
     __syncthreads();   // every wave is done with the previous block
 #pragma unroll
@@ -101,13 +100,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         acc[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sB[(4 * u + lrow) * LDB + kb * 16 + (lane & 15)],
                                                        w[u], acc[kb], 0, 0, 0);
       // w[u] is free once its products are issued: load the next step's entry
-      if (more) {
-        const int row = j + 64 + 4 * u + lrow;
-        if (PADDED)
-          w[u] = W[(int64_t)row * ld + col];
-        else
-          w[u] = (row < n && col < n) ? W[(int64_t)row * ld + col] : 0.0;
-      }
+      if (more) w[u] = w_at(j + 64 + 4 * u + lrow);
     }
   }
   double* out = part + (int64_t)chunk * npad * ldk + (int64_t)col * ldk;
@@ -116,7 +109,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
     for (int v = 0; v < 4; ++v) out[kb * 16 + lrow + 4 * v] = acc[kb][v];
   }
-#undef LOAD_STEP
 }
 
 // FP32 form of the pass for W stored in single precision (precision form):
