@@ -140,6 +140,48 @@ def test_project_ragged_leading_dimension(torch_cuda):
     assert np.abs(P.cpu().numpy() - O.aproj_psd(S, 3)).max() <= 1e-9 * np.abs(lam).max()
 
 
+# ------------------------------------------------- full size, bench setup
+def test_full_size_maxcut_solve_in_the_benchmark_configuration(torch_cuda):
+    """n = 5000 max-cut on G(5000, 0.01), seed 0, FP64 to 1e-4 with the library
+    defaults: the configuration the benchmark times (rank path 1 -> 64, k = 64
+    dense passes in nine row chunks, 64 x 64 Rayleigh-Ritz).  At this size the
+    oracle checks properties of the answer that hold at any size (Section 2.2:
+    the residuals of one exact PDHG step from it; Section 1.3: a certified
+    bracket on the max-cut value) and computes sampled outputs one by one
+    (entries of the dense X written by the tile kernel against
+    sum_t lambda_t V_it V_jt from the returned factors, and its diagonal)."""
+    from paper_1810_05231_amd import Solver
+    _say("full size maxcut", 5000)
+    prob = I.maxcut(5000, 0.01, 0)
+    s = Solver(prob, tol=1e-4)
+    info = s.solve()
+    _say("  info", info["status_name"], info["iters"], info["r"], info["k"], info["rho_p"],
+         info["rho_d"], info["obj"])
+    assert info["status_name"] == "converged"
+    assert info["k"] == 64 and info["r"] == 64
+    X, y = s.solution(on_device=False)
+    V, lam = s.factors()
+    s.close()
+    # sampled entries of the dense write, and the full diagonal
+    rng = np.random.default_rng(11)
+    i = rng.integers(0, 5000, 4000)
+    j = rng.integers(0, 5000, 4000)
+    ref = np.einsum("st,t,st->s", V[i], lam, V[j])
+    scale = max(1.0, np.abs(lam).max())
+    _say("  sampled X", np.abs(X[i, j] - ref).max() / scale)
+    assert np.abs(X[i, j] - ref).max() <= 1e-12 * scale
+    assert np.abs(np.einsum("it,t,it->i", V, lam, V) - np.diag(X)).max() <= 1e-12 * scale
+    # the oracle's exact-step certificate and max-cut bracket of the answer
+    c = O.certificate(prob, X, y)
+    lo, up = O.maxcut_bracket(prob, X, y)
+    _say("  certificate", c.rho_p, c.rho_d, "bracket", lo, up)
+    assert max(c.rho_p, c.rho_d) <= 2e-4
+    assert c.lambda_min_X >= -1e-9
+    assert lo <= up
+    # the reported objective lies within the tolerance's reach of the bracket
+    assert lo - 1e-3 * abs(lo) <= info["obj"] <= up + 1e-3 * abs(up)
+
+
 # -------------------------------------------------------------- iterates
 def _oracle_steps(prob, K, r, alpha):
     ops = O.Operators(prob)
