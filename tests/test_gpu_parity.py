@@ -141,19 +141,22 @@ def test_project_ragged_leading_dimension(torch_cuda):
 
 
 # ------------------------------------------------- full size, bench setup
-def test_full_size_maxcut_solve_in_the_benchmark_configuration(torch_cuda):
-    """n = 5000 max-cut on G(5000, 0.01), seed 0, FP64 to 1e-4 with the library
+@pytest.mark.parametrize("prec", [0, 2, 3], ids=["fp64", "bf16", "implicit"])
+def test_full_size_maxcut_solve_in_the_benchmark_configuration(torch_cuda, prec):
+    """n = 5000 max-cut on G(5000, 0.01), seed 0, to 1e-4 with the library
     defaults: the configuration the benchmark times (rank path 1 -> 64, k = 64
-    dense passes in nine row chunks, 64 x 64 Rayleigh-Ritz).  At this size the
+    dense passes in nine row chunks, 64 x 64 Rayleigh-Ritz), in the plain FP64
+    form and, as the benchmark reports them beside it, the BF16 precision form
+    and the implicit FP64 form.  At this size the
     oracle checks properties of the answer that hold at any size (Section 2.2:
     the residuals of one exact PDHG step from it; Section 1.3: a certified
     bracket on the max-cut value) and computes sampled outputs one by one
     (entries of the dense X written by the tile kernel against
     sum_t lambda_t V_it V_jt from the returned factors, and its diagonal)."""
     from paper_1810_05231_amd import Solver
-    _say("full size maxcut", 5000)
+    _say("full size maxcut", 5000, "precision", prec)
     prob = I.maxcut(5000, 0.01, 0)
-    s = Solver(prob, tol=1e-4)
+    s = Solver(prob, tol=1e-4, precision=prec)
     info = s.solve()
     _say("  info", info["status_name"], info["iters"], info["r"], info["k"], info["rho_p"],
          info["rho_d"], info["obj"])
