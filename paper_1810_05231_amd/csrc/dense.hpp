@@ -22,7 +22,9 @@ namespace proxsdp {
 // (the four waves share it).  The next step's basis block is loaded into
 // registers when the current step's MFMAs start, and each W entry of the next
 // step as soon as the products that use the register holding the current one
-// are issued (124 VGPRs: 4 waves per SIMD at k = 64).  Measured at n = 5000,
+// are issued (122 VGPRs, no AGPRs: 4 waves per SIMD at k = 64; without the
+// waves-per-EU bound the compiler chose 164 VGPRs + 32 AGPRs, 2 waves per
+// SIMD).  Measured at n = 5000,
 // k = 64: 68.8 us against 79.1 us for per-wave basis loads from L2, and 74.6 us
 // when the next step's W entries load all at once into a second set of
 // registers (3 waves per SIMD); identical results.
@@ -51,10 +53,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int ncols = gridDim.x;
   const int T = ncols * gridDim.y;
   const int L = blockIdx.x + ncols * blockIdx.y;
-  const int e = L & 7, s = L >> 3;
-  int start = 0;
-  for (int q = 0; q < e; ++q) start += (T - q + 7) >> 3;
-  const int item = start + s;
+  const int xcd = L & 7, slot = L >> 3;
+  int start = 0;   // items dealt to the XCDs before this one
+  for (int q = 0; q < xcd; ++q) start += (T - q + 7) >> 3;
+  const int item = start + slot;
   const int chunk = item / ncols;
   const int col = (item - chunk * ncols) * 64 + wave * 16 + (lane & 15);
   const int j0 = chunk * rows_per_chunk;
