@@ -231,6 +231,11 @@ __device__ __forceinline__ int jacobi_eig_db(double* A0, double* A1, int lda, do
   const int groups = nt / np;
   const int bi = tid % np, g0 = tid / np;
   const int nw = nt >> 6;
+  // every thread forms the rotation of its own row pair bi; the rotation of
+  // column pair bj comes from the lane of the same wave whose row pair is bj
+  // (np <= 32 < 64: every wave holds all of them), not recomputed
+  const int wbase = (tid - (tid & 63)) % np;   // row pair of the wave's lane 0
+  const int nbj = (np + groups - 1) / groups;   // same count for every thread
   double* Ain = A0;
   double* Aout = A1;
   auto player = [&](int pos, int rnd) {
@@ -269,16 +274,18 @@ __device__ __forceinline__ int jacobi_eig_db(double* A0, double* A1, int lda, do
     }
     if (!(off > tol_off * tol_off * dg) || !(off > 1e-300)) break;
     for (int rnd = 0; rnd < km1; ++rnd) {
-      if (g0 < groups) {
-        int pi = player(bi, rnd), qi = player(k - 1 - bi, rnd);
-        if (pi > qi) { const int t = pi; pi = qi; qi = t; }
-        double ci, si;
-        jacobi_rotation_fast(Ain[pi * lda + pi], Ain[qi * lda + qi], Ain[pi * lda + qi], ci, si);
-        for (int bj = g0; bj < np; bj += groups) {
+      int pi = player(bi, rnd), qi = player(k - 1 - bi, rnd);
+      if (pi > qi) { const int t = pi; pi = qi; qi = t; }
+      double ci, si;
+      jacobi_rotation_fast(Ain[pi * lda + pi], Ain[qi * lda + qi], Ain[pi * lda + qi], ci, si);
+      for (int x = 0; x < nbj; ++x) {
+        const int bj = g0 + x * groups;
+        int src = (bj < np ? bj : 0) - wbase;
+        if (src < 0) src += np;
+        const double cj = __shfl(ci, src), sj = __shfl(si, src);
+        if (g0 < groups && bj < np) {
           int pj = player(bj, rnd), qj = player(k - 1 - bj, rnd);
           if (pj > qj) { const int t = pj; pj = qj; qj = t; }
-          double cj, sj;
-          jacobi_rotation_fast(Ain[pj * lda + pj], Ain[qj * lda + qj], Ain[pj * lda + qj], cj, sj);
           const double a = Ain[pi * lda + pj], b = Ain[pi * lda + qj];
           const double c_ = Ain[qi * lda + pj], d = Ain[qi * lda + qj];
           const double a1 = ci * a - si * c_, b1 = ci * b - si * d;
@@ -288,12 +295,12 @@ __device__ __forceinline__ int jacobi_eig_db(double* A0, double* A1, int lda, do
           Aout[qi * lda + pj] = cj * c1 - sj * d1;
           Aout[qi * lda + qj] = sj * c1 + cj * d1;
         }
-        if (si != 0.0) {
-          for (int r0 = g0; r0 < k; r0 += groups) {
-            const double up = U[r0 * ldu + pi], uq = U[r0 * ldu + qi];
-            U[r0 * ldu + pi] = ci * up - si * uq;
-            U[r0 * ldu + qi] = si * up + ci * uq;
-          }
+      }
+      if (g0 < groups && si != 0.0) {
+        for (int r0 = g0; r0 < k; r0 += groups) {
+          const double up = U[r0 * ldu + pi], uq = U[r0 * ldu + qi];
+          U[r0 * ldu + pi] = ci * up - si * uq;
+          U[r0 * ldu + qi] = si * up + ci * uq;
         }
       }
       __syncthreads();
